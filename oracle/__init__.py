@@ -1,0 +1,197 @@
+"""FP64 CPU oracle (test infrastructure, not the product).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package. It wraps ``oracle.c`` (plain C, double precision,
+no FMA contraction) through ctypes on numpy arrays, and shares nothing with
+the GPU library or its Python binding.
+
+Functions (the C file documents the formulas and the passages they follow):
+
+* :func:`project`         Sec. 2 projection + nearest-depth z-buffer
+* :func:`densify`         Eq. 1-4 gather (common factor exp(Emax) removed)
+* :func:`densify_plain`   Eq. 1-4 literally (no rescaling)
+* :func:`densify_alg1`    Algorithm 1 steps 1-5 (materialised weights)
+* :func:`densify_grad`    gradient w.r.t. depths, sigma_s, sigma_r
+* :func:`l1_holdout_loss` the self-supervised held-out L1 loss and its
+                          upstream gradient
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GCC_FLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+             "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("ORACLE_LIB", _LIB)
+        if path == _LIB and not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(path)
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        vp = C.c_void_p
+        L.oracle_project.restype = C.c_int64
+        L.oracle_project.argtypes = [f32p, C.c_int64, f64p, f64p, C.c_int32,
+                                     C.c_int32, u64p, f32p, u8p]
+        L.oracle_densify.restype = C.c_int64
+        L.oracle_densify.argtypes = [f32p, u8p, u8p, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_double, C.c_double, f64p,
+                                     u8p, vp, vp, vp]
+        L.oracle_densify_plain.restype = None
+        L.oracle_densify_plain.argtypes = [f32p, u8p, u8p, C.c_int32,
+                                           C.c_int32, C.c_int32, C.c_double,
+                                           C.c_double, f64p, u8p]
+        L.oracle_densify_alg1.restype = C.c_int
+        L.oracle_densify_alg1.argtypes = [f32p, u8p, u8p, C.c_int32,
+                                          C.c_int32, C.c_int32, C.c_double,
+                                          C.c_double, f64p, u8p]
+        L.oracle_densify_grad.restype = None
+        L.oracle_densify_grad.argtypes = [f32p, u8p, u8p, C.c_int32,
+                                          C.c_int32, C.c_int32, C.c_double,
+                                          C.c_double, f64p, f64p,
+                                          C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+        L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def project(points, pose, intrinsics, width: int, height: int):
+    """Returns (keys uint64 HxW, depth float32 HxW, valid uint8 HxW, landed).
+
+    ``intrinsics`` is (fx, fy, cx, cy); ``pose`` is camera-from-world 3x4.
+    """
+    pts = _c(points, np.float32).reshape(-1, 3)
+    pose = _c(pose, np.float64).reshape(12)
+    intr = _c(intrinsics[:4], np.float64)
+    keys = np.empty((height, width), np.uint64)
+    depth = np.empty((height, width), np.float32)
+    valid = np.empty((height, width), np.uint8)
+    landed = lib().oracle_project(pts, pts.shape[0], pose, intr, width,
+                                  height, keys, depth, valid)
+    return keys, depth, valid, int(landed)
+
+
+def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
+            want_stats: bool = False):
+    """Eq. 1-4 in double. Returns (out float64 HxW, mask uint8 HxW) and, with
+    ``want_stats``, a dict with per-pixel count, weight sum, Emax and the
+    number of (pixel, sample) pairs."""
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    b = _c(valid, np.uint8)
+    c = _c(rgb, np.uint8).reshape(h, w, 3)
+    out = np.empty((h, w), np.float64)
+    mask = np.empty((h, w), np.uint8)
+    if want_stats:
+        cnt = np.empty((h, w), np.int32)
+        ws = np.empty((h, w), np.float64)
+        em = np.empty((h, w), np.float64)
+        pairs = lib().oracle_densify(d, b, c, h, w, radius, sigma_s, sigma_r,
+                                     out, mask, cnt.ctypes.data,
+                                     ws.ctypes.data, em.ctypes.data)
+        return out, mask, dict(count=cnt, wsum=ws, emax=em, pairs=int(pairs))
+    lib().oracle_densify(d, b, c, h, w, radius, sigma_s, sigma_r, out, mask,
+                         None, None, None)
+    return out, mask
+
+
+def densify_plain(depth, valid, rgb, radius, sigma_s, sigma_r):
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    out = np.empty((h, w), np.float64)
+    mask = np.empty((h, w), np.uint8)
+    lib().oracle_densify_plain(d, _c(valid, np.uint8),
+                               _c(rgb, np.uint8).reshape(h, w, 3), h, w,
+                               radius, sigma_s, sigma_r, out, mask)
+    return out, mask
+
+
+def densify_alg1(depth, valid, rgb, radius, sigma_s, sigma_r):
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    if h * w * (2 * radius + 1) ** 2 > 50_000_000:
+        raise ValueError("Algorithm 1 oracle materialises H*W*(2r+1)^2 "
+                         "weights; input too large")
+    out = np.empty((h, w), np.float64)
+    mask = np.empty((h, w), np.uint8)
+    rc = lib().oracle_densify_alg1(d, _c(valid, np.uint8),
+                                   _c(rgb, np.uint8).reshape(h, w, 3), h, w,
+                                   radius, sigma_s, sigma_r, out, mask)
+    if rc != 0:
+        raise MemoryError("oracle_densify_alg1: allocation failed")
+    return out, mask
+
+
+def densify_grad(depth, valid, rgb, radius, sigma_s, sigma_r, g):
+    """Returns (grad_depth float64 HxW, grad_sigma_s, grad_sigma_r)."""
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    gd = np.empty((h, w), np.float64)
+    gs = C.c_double()
+    gr = C.c_double()
+    lib().oracle_densify_grad(d, _c(valid, np.uint8),
+                              _c(rgb, np.uint8).reshape(h, w, 3), h, w,
+                              radius, sigma_s, sigma_r, _c(g, np.float64), gd,
+                              C.byref(gs), C.byref(gr))
+    return gd, gs.value, gr.value
+
+
+def l1_holdout_loss(outs, masks, targets, target_valid):
+    """Mean absolute error over held-out targets whose output pixel is valid.
+
+    ``outs``/``masks`` are per-frame dense outputs, ``targets`` the held-out
+    depths rasterised through their own z-buffer and ``target_valid`` their
+    presence masks. Returns (loss, list of dL/d out per frame); sign(0) = 0.
+    """
+    use = [(tv == 1) & (m == 1) for tv, m in zip(target_valid, masks)]
+    n = int(sum(int(u.sum()) for u in use))
+    if n == 0:
+        return 0.0, [np.zeros_like(o) for o in outs]
+    loss = 0.0
+    grads = []
+    for o, t, u in zip(outs, targets, use):
+        diff = np.where(u, o - t.astype(np.float64), 0.0)
+        loss += float(np.abs(diff).sum())
+        grads.append(np.sign(diff) / n)
+    return loss / n, grads
