@@ -1,0 +1,205 @@
+/*
+ * jbfd.h - C ABI of the MI355X (gfx950) LiDAR depth-densification library.
+ *
+ * The library implements the data-parallel hot path of "Real-Time LiDAR
+ * Point Cloud Densification for Low-Latency Spatial Data Transmission"
+ * (arXiv 2601.01210):
+ *
+ *   1. jbfd_project  - merged LiDAR points are projected into the camera
+ *                      view to form one sparse depth image (Sec. 2), with a
+ *                      nearest-depth z-buffer;
+ *   2. jbfd_densify  - RGB-guided joint bilateral filter over that sparse
+ *                      depth image (Eq. 1-4, organised as Algorithm 1),
+ *                      giving a dense depth image and a validity mask;
+ *   3. jbfd_densify_backward - gradients of a loss through the filter with
+ *                      respect to the input depths and the two Gaussian
+ *                      widths (Sec. 4: the filter parameters are trainable
+ *                      by backpropagation);
+ *   4. jbfd_batch_run - projection + filter for many viewpoints of mixed
+ *                      size in one persistent launch (Sec. 2 processes each
+ *                      viewpoint independently).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every buffer pointer is a DEVICE pointer unless stated otherwise. The
+ *   caller allocates and frees every buffer; the library never allocates
+ *   device memory and keeps no mutable global state, so calls on different
+ *   streams may run concurrently from different host threads.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *   work is enqueued asynchronously on it; outputs are valid once the caller
+ *   has synchronised the stream.
+ * - Images are row-major, H rows by W columns; pixel (col,row) is at index
+ *   row*W + col. RGB is interleaved 8-bit (3 bytes per pixel, R first).
+ * - Argument errors are detected on the host before anything is enqueued
+ *   and returned as JBFD_EINVAL; no output is touched then. Launch failures
+ *   return JBFD_EHIP with a message in jbfd_last_error(). Faults inside a
+ *   kernel surface at the caller's next synchronisation (HIP semantics).
+ *   No C++ exception crosses this interface.
+ * - Readings of what the paper leaves open (the same ones the CPU oracle
+ *   uses): depth is camera-frame Z; pixel (col,row) covers u in [col,col+1),
+ *   v in [row,row+1); the nearest point wins a pixel and an exact float tie
+ *   goes to the smaller point index; the filter window is the full
+ *   (2r+1)x(2r+1) square including its centre, clipped at the border;
+ *   colour distance is the squared L2 norm of raw 0..255 RGB; an output
+ *   pixel is valid iff its window holds at least one valid sample; invalid
+ *   pixels hold depth 0.
+ */
+#ifndef JBFD_H
+#define JBFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JBFD_ABI_VERSION 1
+
+/* Largest filter radius: the halo of one 8x8 output block must fit the
+ * per-workgroup spatial table in LDS. */
+#define JBFD_MAX_RADIUS 32
+
+/* Smallest accepted sigma (pixels for sigma_s, RGB units for sigma_r). Below
+ * it the log2-domain weight exponent of a far sample would exceed the range
+ * in which the FP32 kernels keep it exact. */
+#define JBFD_MIN_SIGMA 0.25f
+
+typedef enum jbfd_status {
+    JBFD_OK = 0,
+    JBFD_EINVAL = 1,      /* bad argument (null pointer, size, radius, sigma) */
+    JBFD_EUNSUPPORTED = 2, /* valid request this build does not implement */
+    JBFD_EHIP = 3,        /* HIP runtime or launch error, see jbfd_last_error */
+    JBFD_ENOSPC = 4       /* caller workspace smaller than the queried size */
+} jbfd_status;
+
+typedef enum jbfd_precision {
+    JBFD_FP32 = 0,        /* weights, sums and divide in FP32 */
+    JBFD_FP16_RANGE = 1   /* colour differences and range weights in FP16,
+                             spatial weight, depth, sums, divide in FP32 */
+} jbfd_precision;
+
+/* Pinhole intrinsics of a camera and the size of its image. */
+typedef struct jbfd_intrinsics {
+    double fx, fy;        /* focal lengths in pixels */
+    double cx, cy;        /* principal point, pixel-edge convention
+                             (a centred camera has cx = W/2) */
+    int32_t width;        /* W, 1 .. 65535 */
+    int32_t height;       /* H, 1 .. 65535 */
+} jbfd_intrinsics;
+
+/* Version of this interface (JBFD_ABI_VERSION of the built library). */
+int jbfd_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *jbfd_status_string(jbfd_status s);
+
+/* Message of the last error on the calling thread ("" if none). The pointer
+ * stays valid until the next call into the library on this thread. */
+const char *jbfd_last_error(void);
+
+/*
+ * Projection of merged LiDAR points into one camera and nearest-depth
+ * z-buffer (Sec. 2: "merged and projected into the camera view to form a
+ * single depth image"; the collision rule is the reading stated above).
+ *
+ * For each point i (its index in the merged array, sweeps concatenated in
+ * order): (X,Y,Z) = R p + t in double precision, summed left to right with
+ * no fused multiply-add; the point is dropped unless Z > 0 and finite;
+ * u = fx*(X/Z) + cx, v = fy*(Y/Z) + cy; dropped unless 0 <= u < W and
+ * 0 <= v < H; zf = (float)Z (round to nearest even), dropped if zf == 0 or
+ * infinite; key = (bits(zf) << 32) | i competes for pixel (floor u, floor v)
+ * and the smallest key wins (atomicMin on the 64-bit key).
+ *
+ * pts_xyz         n x 3 float32 world coordinates (device), any alignment
+ *                 of 4 bytes; non-finite points are culled, not an error
+ * n               number of points, 0 <= n < 2^32
+ * cam_from_world  12 doubles, row-major 3x4 [R|t] (HOST memory, read during
+ *                 the call); must be finite
+ * K               intrinsics and image size (HOST memory); fx, fy, cx, cy
+ *                 finite
+ * zbuf            W*H uint64 workspace/output (device): the winning key per
+ *                 pixel, UINT64_MAX where no point landed; cleared by this
+ *                 call
+ * sparse_depth    W*H float32 output (device): float Z of the winner, 0.0f
+ *                 where empty; may be NULL
+ * sparse_valid    W*H uint8 output (device): 1 where a point landed, else 0;
+ *                 may be NULL
+ */
+jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
+                         const double cam_from_world[12],
+                         const jbfd_intrinsics *K, uint64_t *zbuf,
+                         float *sparse_depth, uint8_t *sparse_valid,
+                         void *stream);
+
+/*
+ * Joint bilateral filter over a sparse depth image (Eq. 1-4; the window and
+ * step structure of Algorithm 1).
+ *
+ * For each pixel x, over the valid samples n (sparse_valid == 1) of the
+ * (2r+1)x(2r+1) window around x, clipped to the image:
+ *     w(x,n) = exp(-|I(x)-I(n)|^2 / (2 sigma_r^2)) * exp(-|x-n|^2 / (2 sigma_s^2))
+ *     dense_depth(x) = sum w D(n) / sum w,   dense_valid(x) = 1
+ * and dense_depth(x) = 0, dense_valid(x) = 0 when the window holds no valid
+ * sample. sparse_depth is read only where sparse_valid == 1. The kernels
+ * divide all weights of one output pixel by a common power of two that
+ * keeps them in range; it cancels in the ratio.
+ *
+ * sparse_depth, sparse_valid  H*W float32 / uint8 (device)
+ * rgb_hwc         H*W*3 uint8 guide image (device)
+ * H, W            1 .. 65535 each
+ * radius          0 .. JBFD_MAX_RADIUS
+ * sigma_s         spatial width in pixels, >= JBFD_MIN_SIGMA or +inf
+ * sigma_r         colour width in RGB units, >= JBFD_MIN_SIGMA or +inf
+ * prec            JBFD_FP32 or JBFD_FP16_RANGE
+ * dense_depth     H*W float32 output (device)
+ * dense_valid     H*W uint8 output (device)
+ * aux             NULL, or H*W*2 float32 output (device) saved for
+ *                 jbfd_densify_backward: per pixel the integer log2 shift
+ *                 and the shifted weight sum (FP32 precision only)
+ */
+jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,
+                         const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                         int32_t radius, float sigma_s, float sigma_r,
+                         jbfd_precision prec, float *dense_depth,
+                         uint8_t *dense_valid, float *aux, void *stream);
+
+/*
+ * Gradient of a scalar loss L through jbfd_densify (FP32 precision).
+ *
+ * With w_i the weights of the valid samples i in the window of x,
+ * W(x) = sum w_i and out(x) = dense_depth(x):
+ *     dL/dD_i      += g(x) w_i / W(x)
+ *     dL/dsigma_r  += g(x) sum_i w_i c_i (D_i - out(x)) / (sigma_r^3 W(x))
+ *     dL/dsigma_s  += g(x) sum_i w_i s_i (D_i - out(x)) / (sigma_s^3 W(x))
+ * where c_i is the squared colour distance, s_i the squared pixel distance
+ * and g = grad_out. Pixels with dense_valid == 0 contribute nothing.
+ *
+ * The forward inputs and parameters must be the ones of the jbfd_densify
+ * call that produced dense_depth and aux.
+ * grad_out        H*W float32 (device), dL/d dense_depth
+ * grad_depth      H*W float32 output (device), dL/d sparse_depth (0 where
+ *                 sparse_valid == 0); overwritten
+ * grad_sigmas     2 doubles output (device): dL/dsigma_s, dL/dsigma_r;
+ *                 overwritten; 0 for an infinite sigma
+ * ws, ws_bytes    device workspace of at least
+ *                 jbfd_densify_backward_ws_bytes(H, W) bytes; the sigma
+ *                 reduction is deterministic (fixed order)
+ */
+jbfd_status jbfd_densify_backward(const float *sparse_depth,
+                                  const uint8_t *sparse_valid,
+                                  const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                                  int32_t radius, float sigma_s, float sigma_r,
+                                  const float *dense_depth, const float *aux,
+                                  const float *grad_out, float *grad_depth,
+                                  double *grad_sigmas, void *ws,
+                                  size_t ws_bytes, void *stream);
+
+/* Workspace bytes needed by jbfd_densify_backward for an H x W image. */
+size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JBFD_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) LiDAR depth densification: nearest-depth projection and
+RGB-guided joint bilateral filtering (arXiv 2601.01210), as hand-written HIP
+kernels behind the C ABI in include/jbfd.h.
+
+The Python layer only marshals arguments (torch tensors for device memory
+and streams) into the C library; every step of the computation runs in the
+HIP kernels. There is no CPU fallback: if libjbfd.so is missing the calls
+raise.
+"""
+from .binding import (JbfdError, Precision, abi_version, densify,  # noqa: F401
+                      densify_backward, library_path, project)

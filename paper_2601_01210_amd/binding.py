@@ -1,0 +1,221 @@
+"""ctypes binding of libjbfd.so (argument marshalling only).
+
+Each function takes and returns torch tensors on the current HIP device and
+enqueues work on torch's current stream; it validates shapes and dtypes so
+that the C library receives exactly the layouts include/jbfd.h documents.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import enum
+import math
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libjbfd.so")
+
+JBFD_OK, JBFD_EINVAL, JBFD_EUNSUPPORTED, JBFD_EHIP, JBFD_ENOSPC = range(5)
+
+
+class Precision(enum.IntEnum):
+    FP32 = 0
+    FP16_RANGE = 1
+
+
+class JbfdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"jbfd status {status}: {message}")
+        self.status = status
+
+
+class Intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double),
+                ("cy", C.c_double), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libjbfd.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: build it with "
+                "`python -m paper_2601_01210_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(_LIB_PATH)
+        vp, i32, i64, f32, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_float,
+                                 C.c_size_t)
+        L.jbfd_abi_version.restype = C.c_int
+        L.jbfd_status_string.restype = C.c_char_p
+        L.jbfd_status_string.argtypes = [C.c_int]
+        L.jbfd_last_error.restype = C.c_char_p
+        L.jbfd_project.restype = C.c_int
+        L.jbfd_project.argtypes = [vp, i64, C.POINTER(C.c_double),
+                                   C.POINTER(Intrinsics), vp, vp, vp, vp]
+        L.jbfd_densify.restype = C.c_int
+        L.jbfd_densify.argtypes = [vp, vp, vp, i32, i32, i32, f32, f32,
+                                   C.c_int, vp, vp, vp, vp]
+        L.jbfd_densify_backward.restype = C.c_int
+        L.jbfd_densify_backward.argtypes = [vp, vp, vp, i32, i32, i32, f32,
+                                            f32, vp, vp, vp, vp, vp, vp, sz,
+                                            vp]
+        L.jbfd_densify_backward_ws_bytes.restype = sz
+        L.jbfd_densify_backward_ws_bytes.argtypes = [i32, i32]
+        _lib = L
+    return _lib
+
+
+def abi_version() -> int:
+    return lib().jbfd_abi_version()
+
+
+def _check(status: int):
+    if status != JBFD_OK:
+        msg = lib().jbfd_last_error().decode()
+        raise JbfdError(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device=None):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _need(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got "
+                         f"{tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _pose_array(pose) -> C.Array:
+    a = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(12))
+    return (C.c_double * 12)(*a.tolist())
+
+
+def project(points, pose, intrinsics: Sequence[float], width: int,
+            height: int, zbuf=None, depth=None, valid=None,
+            want_sparse: bool = True):
+    """Nearest-depth projection (jbfd_project).
+
+    points      (N,3) float32 device tensor, world xyz in merged order
+    pose        3x4 camera-from-world [R|t] (host array-like)
+    intrinsics  (fx, fy, cx, cy)
+    Returns (zbuf uint64-as-int64 (H,W), depth float32 (H,W), valid uint8
+    (H,W)); depth/valid are None when ``want_sparse`` is False.
+    """
+    torch = _torch()
+    _need(points, torch.float32, None, "points")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (N, 3)")
+    dev = points.device
+    if zbuf is None:
+        zbuf = torch.empty((height, width), dtype=torch.int64, device=dev)
+    _need(zbuf, torch.int64, (height, width), "zbuf")
+    if want_sparse:
+        if depth is None:
+            depth = torch.empty((height, width), dtype=torch.float32, device=dev)
+        if valid is None:
+            valid = torch.empty((height, width), dtype=torch.uint8, device=dev)
+        _need(depth, torch.float32, (height, width), "depth")
+        _need(valid, torch.uint8, (height, width), "valid")
+    K = Intrinsics(float(intrinsics[0]), float(intrinsics[1]),
+                   float(intrinsics[2]), float(intrinsics[3]), int(width),
+                   int(height))
+    _check(lib().jbfd_project(_ptr(points), int(points.shape[0]),
+                              _pose_array(pose), C.byref(K), _ptr(zbuf),
+                              _ptr(depth), _ptr(valid), _stream(dev)))
+    return zbuf, depth, valid
+
+
+def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
+            precision: Precision = Precision.FP32, out=None, mask=None,
+            aux=None, want_aux: bool = False):
+    """Joint bilateral filter (jbfd_densify).
+
+    depth (H,W) float32, valid (H,W) uint8, rgb (H,W,3) uint8, all on the
+    device. Returns (dense depth float32, mask uint8[, aux float32 (H,W,2)]).
+    """
+    torch = _torch()
+    _need(depth, torch.float32, None, "depth")
+    if depth.dim() != 2:
+        raise ValueError("depth must be (H, W)")
+    h, w = depth.shape
+    _need(valid, torch.uint8, (h, w), "valid")
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    dev = depth.device
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if mask is None:
+        mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    _need(out, torch.float32, (h, w), "out")
+    _need(mask, torch.uint8, (h, w), "mask")
+    if want_aux and aux is None:
+        aux = torch.empty((h, w, 2), dtype=torch.float32, device=dev)
+    if aux is not None:
+        _need(aux, torch.float32, (h, w, 2), "aux")
+    _check(lib().jbfd_densify(_ptr(depth), _ptr(valid), _ptr(rgb), h, w,
+                              int(radius), float(sigma_s), float(sigma_r),
+                              int(precision), _ptr(out), _ptr(mask),
+                              _ptr(aux), _stream(dev)))
+    if aux is not None:
+        return out, mask, aux
+    return out, mask
+
+
+def densify_backward(depth, valid, rgb, radius: int, sigma_s: float,
+                     sigma_r: float, out, aux, grad_out, grad_depth=None,
+                     grad_sigmas=None, ws=None):
+    """Gradient through the filter (jbfd_densify_backward).
+
+    Returns (grad_depth float32 (H,W), grad_sigmas float64 (2,) device tensor
+    holding dL/dsigma_s, dL/dsigma_r).
+    """
+    torch = _torch()
+    h, w = depth.shape
+    _need(depth, torch.float32, (h, w), "depth")
+    _need(valid, torch.uint8, (h, w), "valid")
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    _need(out, torch.float32, (h, w), "out")
+    _need(aux, torch.float32, (h, w, 2), "aux")
+    _need(grad_out, torch.float32, (h, w), "grad_out")
+    dev = depth.device
+    if grad_depth is None:
+        grad_depth = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if grad_sigmas is None:
+        grad_sigmas = torch.empty(2, dtype=torch.float64, device=dev)
+    nbytes = int(lib().jbfd_densify_backward_ws_bytes(h, w))
+    if ws is None:
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().jbfd_densify_backward(
+        _ptr(depth), _ptr(valid), _ptr(rgb), h, w, int(radius),
+        float(sigma_s), float(sigma_r), _ptr(out), _ptr(aux), _ptr(grad_out),
+        _ptr(grad_depth), _ptr(grad_sigmas), _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return grad_depth, grad_sigmas

@@ -1,0 +1,169 @@
+// C ABI of libjbfd (declared in include/jbfd.h): argument validation on the
+// host, then asynchronous launches on the caller's stream. No entry point
+// allocates device memory; errors are returned as status codes with a
+// thread-local message.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "jbfd_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+jbfd_status fail(jbfd_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+jbfd_status ok() {
+    g_err[0] = '\0';
+    return JBFD_OK;
+}
+
+jbfd_status hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return ok();
+    return fail(JBFD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool sigma_ok(float s) {
+    if (isnan(s)) return false;
+    if (isinf(s)) return s > 0;
+    return s >= JBFD_MIN_SIGMA;
+}
+
+// log2(e) / (2 sigma^2), 0 for an infinite sigma
+float log2_half_inv_var(float sigma) {
+    if (isinf(sigma)) return 0.0f;
+    const double s = (double)sigma;
+    return (float)(1.4426950408889634 / (2.0 * s * s));
+}
+
+jbfd_status check_image(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0 || H > 65535 || W > 65535)
+        return fail(JBFD_EINVAL, "image size %d x %d outside 1..65535", H, W);
+    return JBFD_OK;
+}
+
+jbfd_status check_filter(int32_t radius, float ss, float sr) {
+    if (radius < 0 || radius > JBFD_MAX_RADIUS)
+        return fail(JBFD_EINVAL, "radius %d outside 0..%d", radius,
+                    JBFD_MAX_RADIUS);
+    if (!sigma_ok(ss))
+        return fail(JBFD_EINVAL, "sigma_s %g must be >= %g or +inf", (double)ss,
+                    (double)JBFD_MIN_SIGMA);
+    if (!sigma_ok(sr))
+        return fail(JBFD_EINVAL, "sigma_r %g must be >= %g or +inf", (double)sr,
+                    (double)JBFD_MIN_SIGMA);
+    return JBFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jbfd_abi_version(void) { return JBFD_ABI_VERSION; }
+
+const char *jbfd_status_string(jbfd_status s) {
+    switch (s) {
+    case JBFD_OK: return "ok";
+    case JBFD_EINVAL: return "invalid argument";
+    case JBFD_EUNSUPPORTED: return "unsupported";
+    case JBFD_EHIP: return "HIP runtime error";
+    case JBFD_ENOSPC: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char *jbfd_last_error(void) { return g_err; }
+
+jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
+                         const double cam_from_world[12],
+                         const jbfd_intrinsics *K, uint64_t *zbuf,
+                         float *sparse_depth, uint8_t *sparse_valid,
+                         void *stream) {
+    if (!cam_from_world || !K || !zbuf)
+        return fail(JBFD_EINVAL, "jbfd_project: null pose, intrinsics or zbuf");
+    if (n < 0 || n >= ((int64_t)1 << 32))
+        return fail(JBFD_EINVAL, "jbfd_project: n = %lld outside 0..2^32-1",
+                    (long long)n);
+    if (n > 0 && !pts_xyz)
+        return fail(JBFD_EINVAL, "jbfd_project: null points");
+    jbfd_status st = check_image(K->height, K->width);
+    if (st != JBFD_OK) return st;
+    for (int t = 0; t < 12; ++t)
+        if (!isfinite(cam_from_world[t]))
+            return fail(JBFD_EINVAL, "jbfd_project: pose entry %d not finite", t);
+    if (!isfinite(K->fx) || !isfinite(K->fy) || !isfinite(K->cx) ||
+        !isfinite(K->cy))
+        return fail(JBFD_EINVAL, "jbfd_project: intrinsics not finite");
+    jbfd::Pose P;
+    for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
+    jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
+    return hip_status(jbfd::launch_project(pts_xyz, n, P, I, zbuf, sparse_depth,
+                                           sparse_valid, (hipStream_t)stream),
+                      "jbfd_project");
+}
+
+jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,
+                         const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                         int32_t radius, float sigma_s, float sigma_r,
+                         jbfd_precision prec, float *dense_depth,
+                         uint8_t *dense_valid, float *aux, void *stream) {
+    if (!sparse_depth || !sparse_valid || !rgb_hwc || !dense_depth || !dense_valid)
+        return fail(JBFD_EINVAL, "jbfd_densify: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    st = check_filter(radius, sigma_s, sigma_r);
+    if (st != JBFD_OK) return st;
+    if (prec != JBFD_FP32 && prec != JBFD_FP16_RANGE)
+        return fail(JBFD_EINVAL, "jbfd_densify: unknown precision %d", (int)prec);
+    if (aux && prec != JBFD_FP32)
+        return fail(JBFD_EINVAL, "jbfd_densify: aux is produced by FP32 only");
+    jbfd::FilterParams fp{radius, log2_half_inv_var(sigma_r),
+                          log2_half_inv_var(sigma_s)};
+    hipError_t e = jbfd::launch_densify(sparse_depth, sparse_valid, rgb_hwc, H, W,
+                                        fp, prec, dense_depth, dense_valid, aux,
+                                        (hipStream_t)stream);
+    if (e == hipErrorNotSupported)
+        return fail(JBFD_EUNSUPPORTED, "jbfd_densify: precision not built");
+    return hip_status(e, "jbfd_densify");
+}
+
+jbfd_status jbfd_densify_backward(const float *sparse_depth,
+                                  const uint8_t *sparse_valid,
+                                  const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                                  int32_t radius, float sigma_s, float sigma_r,
+                                  const float *dense_depth, const float *aux,
+                                  const float *grad_out, float *grad_depth,
+                                  double *grad_sigmas, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    if (!sparse_depth || !sparse_valid || !rgb_hwc || !dense_depth || !aux ||
+        !grad_out || !grad_depth || !grad_sigmas || !ws)
+        return fail(JBFD_EINVAL, "jbfd_densify_backward: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    st = check_filter(radius, sigma_s, sigma_r);
+    if (st != JBFD_OK) return st;
+    if (ws_bytes < jbfd::backward_ws_bytes(H, W))
+        return fail(JBFD_ENOSPC, "jbfd_densify_backward: workspace %zu < %zu",
+                    ws_bytes, jbfd::backward_ws_bytes(H, W));
+    jbfd::FilterParams fp{radius, log2_half_inv_var(sigma_r),
+                          log2_half_inv_var(sigma_s)};
+    return hip_status(jbfd::launch_densify_backward(
+                          sparse_depth, sparse_valid, rgb_hwc, H, W, fp, sigma_s,
+                          sigma_r, dense_depth, aux, grad_out, grad_depth,
+                          grad_sigmas, ws, (hipStream_t)stream),
+                      "jbfd_densify_backward");
+}
+
+size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0) return 0;
+    return jbfd::backward_ws_bytes(H, W);
+}
+
+}  // extern "C"

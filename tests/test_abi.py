@@ -1,0 +1,118 @@
+"""C-ABI contract checks that need no GPU.
+
+The library must load, export every function include/jbfd.h declares, and
+reject bad arguments on the host before touching the device (so these
+calls are safe without a GPU: validation precedes any HIP call).
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jbfd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jbfd_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2601_01210_amd import binding
+    return binding.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ["jbfd_project", "jbfd_densify", "jbfd_densify_backward",
+              "jbfd_status_string", "jbfd_last_error", "jbfd_abi_version"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings(L):
+    from paper_2601_01210_amd import binding
+    assert L.jbfd_abi_version() == 1
+    for code in range(5):
+        assert L.jbfd_status_string(code)
+    assert L.jbfd_status_string(99) == b"unknown status"
+
+
+def _K(w=8, h=6):
+    from paper_2601_01210_amd.binding import Intrinsics
+    return Intrinsics(4.0, 4.0, 4.0, 3.0, w, h)
+
+
+def test_project_rejects_bad_arguments(L):
+    from paper_2601_01210_amd.binding import JBFD_EINVAL
+    pose = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    K = _K()
+    assert L.jbfd_project(fake, 10, pose, C.byref(K), None, None, None,
+                          None) == JBFD_EINVAL
+    assert b"zbuf" in L.jbfd_last_error()
+    assert L.jbfd_project(fake, -1, pose, C.byref(K), fake, None, None,
+                          None) == JBFD_EINVAL
+    assert L.jbfd_project(fake, 1 << 32, pose, C.byref(K), fake, None, None,
+                          None) == JBFD_EINVAL
+    assert L.jbfd_project(None, 5, pose, C.byref(K), fake, None, None,
+                          None) == JBFD_EINVAL
+    bad = _K(0, 6)
+    assert L.jbfd_project(fake, 1, pose, C.byref(bad), fake, None, None,
+                          None) == JBFD_EINVAL
+    nanpose = (C.c_double * 12)(1, 0, 0, float("nan"), 0, 1, 0, 0, 0, 0, 1, 0)
+    assert L.jbfd_project(fake, 1, nanpose, C.byref(K), fake, None, None,
+                          None) == JBFD_EINVAL
+    assert b"pose" in L.jbfd_last_error()
+
+
+@pytest.mark.parametrize("radius,ss,sr", [(-1, 3.0, 12.0), (33, 3.0, 12.0),
+                                          (5, 0.1, 12.0), (5, 3.0, 0.0),
+                                          (5, float("nan"), 12.0),
+                                          (5, 3.0, -float("inf"))])
+def test_densify_rejects_bad_filter(L, radius, ss, sr):
+    from paper_2601_01210_amd.binding import JBFD_EINVAL
+    f = C.c_void_p(0x1000)
+    st = L.jbfd_densify(f, f, f, 10, 10, radius, C.c_float(ss), C.c_float(sr),
+                        0, f, f, None, None)
+    assert st == JBFD_EINVAL
+
+
+def test_densify_rejects_sizes_and_nulls(L):
+    from paper_2601_01210_amd.binding import JBFD_EINVAL
+    f = C.c_void_p(0x1000)
+    assert L.jbfd_densify(f, f, f, 0, 10, 2, C.c_float(1), C.c_float(1), 0,
+                          f, f, None, None) == JBFD_EINVAL
+    assert L.jbfd_densify(f, f, f, 10, 70000, 2, C.c_float(1), C.c_float(1),
+                          0, f, f, None, None) == JBFD_EINVAL
+    assert L.jbfd_densify(None, f, f, 10, 10, 2, C.c_float(1), C.c_float(1),
+                          0, f, f, None, None) == JBFD_EINVAL
+    assert L.jbfd_densify(f, f, f, 10, 10, 2, C.c_float(1), C.c_float(1), 7,
+                          f, f, None, None) == JBFD_EINVAL
+    # aux is an FP32-only output
+    assert L.jbfd_densify(f, f, f, 10, 10, 2, C.c_float(1), C.c_float(1), 1,
+                          f, f, f, None) == JBFD_EINVAL
+
+
+def test_backward_workspace_checks(L):
+    from paper_2601_01210_amd.binding import JBFD_EINVAL, JBFD_ENOSPC
+    f = C.c_void_p(0x1000)
+    need = L.jbfd_densify_backward_ws_bytes(100, 100)
+    assert need > 0
+    assert L.jbfd_densify_backward_ws_bytes(0, 100) == 0
+    st = L.jbfd_densify_backward(f, f, f, 100, 100, 3, C.c_float(2),
+                                 C.c_float(10), f, f, f, f, f, f, need - 1,
+                                 None)
+    assert st == JBFD_ENOSPC
+    st = L.jbfd_densify_backward(f, f, f, 100, 100, 3, C.c_float(2),
+                                 C.c_float(10), f, None, f, f, f, f, need,
+                                 None)
+    assert st == JBFD_EINVAL

@@ -1,0 +1,251 @@
+"""GPU parity against the FP64 oracle, through the C ABI.
+
+* projection: z-buffer keys (depth bits | point index), sparse depth and
+  mask bit-exact, on hand-built edge cases, adversarial pixel-edge points
+  and the seeded scenes;
+* filter (FP32): mask bit-exact; every valid pixel within 1e-5 relative of
+  the oracle; depth 0 where the mask is 0; on ragged sizes that span
+  several tiles, radius 0..32, empty and fully dense inputs, extreme sigmas,
+  and full-size small and Full-HD frames.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+def _gpu_project(torch, dev, pts, pose, intr, w, h):
+    from paper_2601_01210_amd import project
+    p = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).to(dev)
+    zbuf, depth, valid = project(p, pose, intr, w, h)
+    torch.cuda.synchronize()
+    return (zbuf.cpu().numpy().view(np.uint64), depth.cpu().numpy(),
+            valid.cpu().numpy())
+
+
+def _check_projection(torch, dev, pts, pose, intr, w, h):
+    keys, depth, valid, _ = oracle.project(pts, pose, intr, w, h)
+    gk, gd, gv = _gpu_project(torch, dev, pts, pose, intr, w, h)
+    np.testing.assert_array_equal(gk, keys)
+    np.testing.assert_array_equal(gd.view(np.uint32), depth.view(np.uint32))
+    np.testing.assert_array_equal(gv, valid)
+    return keys
+
+
+def test_project_golden_cases(torch_dev):
+    torch, dev = torch_dev
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "projection_cases.json")
+    for case in json.load(open(path))["cases"]:
+        pts = np.array([[np.float32(float(v) if v in ("nan", "inf") else
+                                    float.fromhex(v)) for v in p]
+                        for p in case["points"]], np.float32)
+        pose = np.array([[float.fromhex(v) if isinstance(v, str) else float(v)
+                          for v in row] for row in case["pose"]])
+        print("golden case", case["name"], flush=True)
+        _check_projection(torch, dev, pts, pose, case["intrinsics"],
+                          case["width"], case["height"])
+
+
+def test_project_pixel_edges(torch_dev):
+    """Points whose u, v sit exactly on, or one float32 step either side of,
+    pixel edges; depths from a few values so that exact ties occur."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(0)
+    w, h = 97, 61
+    n = 20000
+    col = rng.integers(-1, w + 1, size=n).astype(np.float64)
+    row = rng.integers(-1, h + 1, size=n).astype(np.float64)
+    z = rng.choice([0.5, 1.0, 2.0, 3.0, 7.25], size=n)
+    x = np.float32((col - w / 2.0) * z / 40.0)
+    y = np.float32((row - h / 2.0) * z / 40.0)
+    nudge = rng.integers(-1, 2, size=(n, 2))
+    x = np.nextafter(x, np.float32(np.inf) * nudge[:, 0]).astype(np.float32)
+    y = np.nextafter(y, np.float32(np.inf) * nudge[:, 1]).astype(np.float32)
+    pts = np.stack([x, y, z.astype(np.float32)], axis=1)
+    pose = np.hstack([np.eye(3), np.zeros((3, 1))])
+    _check_projection(torch, dev, pts, pose, (40.0, 40.0, w / 2.0, h / 2.0),
+                      w, h)
+
+
+def test_project_rotated_pose_random(torch_dev):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(1)
+    a = 0.3
+    rot = np.array([[math.cos(a), 0, math.sin(a)], [0, 1, 0],
+                    [-math.sin(a), 0, math.cos(a)]])
+    pose = np.hstack([rot, np.array([[0.1], [-0.2], [0.5]])])
+    pts = rng.normal(0, 3, size=(50000, 3)).astype(np.float32)
+    pts[:, 2] = np.abs(pts[:, 2]) + 0.5
+    pts[::97] = np.nan
+    pts[1::89, 2] = -1.0
+    _check_projection(torch, dev, pts, pose, (300.0, 280.0, 320.0, 240.0),
+                      640, 480)
+
+
+def test_project_empty_and_keys_only(torch_dev):
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import project
+    pts = torch.zeros((0, 3), dtype=torch.float32, device=dev)
+    zbuf, d, v = project(pts, np.hstack([np.eye(3), np.zeros((3, 1))]),
+                         (4.0, 4.0, 4.0, 3.0), 8, 6)
+    torch.cuda.synchronize()
+    assert np.all(zbuf.cpu().numpy().view(np.uint64) == np.uint64(2 ** 64 - 1))
+    assert np.all(d.cpu().numpy() == 0) and np.all(v.cpu().numpy() == 0)
+    pts = torch.tensor([[0.0, 0.0, 2.0]], device=dev)
+    zbuf, d, v = project(pts, np.hstack([np.eye(3), np.zeros((3, 1))]),
+                         (4.0, 4.0, 4.0, 3.0), 8, 6, want_sparse=False)
+    torch.cuda.synchronize()
+    assert d is None and v is None
+    k = zbuf.cpu().numpy().view(np.uint64)
+    assert k[3, 4] == (np.float32(2.0).view(np.uint32).astype(np.uint64) << 32)
+
+
+def test_project_scenes(torch_dev):
+    torch, dev = torch_dev
+    for name, f in [("small", S.small_view(S.seeded(1))),
+                    ("fullhd", S.fullhd_view(S.seeded(2)))]:
+        print("projection scene", name, len(f.points), flush=True)
+        cam = f.camera
+        _check_projection(torch, dev, f.points, cam.pose, cam.intrinsics(),
+                          cam.width, cam.height)
+
+
+# ---------------------------------------------------------------------------
+# filter
+# ---------------------------------------------------------------------------
+
+
+def _gpu_densify(torch, dev, d, b, rgb, r, ss, sr, prec=0):
+    from paper_2601_01210_amd import densify
+    td = torch.from_numpy(np.ascontiguousarray(d, np.float32)).to(dev)
+    tb = torch.from_numpy(np.ascontiguousarray(b, np.uint8)).to(dev)
+    tc = torch.from_numpy(np.ascontiguousarray(rgb, np.uint8)).to(dev)
+    out, mask = densify(td, tb, tc, r, ss, sr, precision=prec)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), mask.cpu().numpy()
+
+
+def check_filter(torch, dev, d, b, rgb, r, ss, sr, tol=REL_TOL):
+    ref, rmask = oracle.densify(d, b, rgb, r, ss, sr)
+    out, mask = _gpu_densify(torch, dev, d, b, rgb, r, ss, sr)
+    np.testing.assert_array_equal(mask, rmask)
+    sel = mask == 1
+    assert np.all(out[~sel] == 0.0)
+    err = np.abs(out[sel].astype(np.float64) - ref[sel])
+    rel = err / np.abs(ref[sel])
+    worst = float(rel.max()) if rel.size else 0.0
+    print(f"  r={r} ss={ss} sr={sr} shape={d.shape} valid={int(sel.sum())} "
+          f"max_rel={worst:.3e}", flush=True)
+    assert worst <= tol
+    return out, mask, worst
+
+
+FILTER_CASES = [
+    # h, w, r, density, sigma_s, sigma_r, palette
+    (1, 1, 0, 1.0, 1.0, 1.0, None),
+    (1, 37, 3, 0.3, 2.0, 12.0, 3),
+    (37, 1, 3, 0.3, 2.0, 12.0, 3),
+    (17, 23, 2, 0.2, 1.5, 12.0, None),
+    (40, 53, 5, 0.07, 3.0, 12.0, 4),
+    (64, 64, 15, 0.07, 6.0, 15.0, 5),
+    (71, 90, 32, 0.05, 8.0, 20.0, 4),
+    (100, 130, 7, 1.0, 3.0, 12.0, 6),        # every pixel valid
+    (33, 47, 4, 0.0, 2.0, 12.0, None),        # nothing valid
+    (45, 61, 6, 0.1, math.inf, 10.0, 3),      # pure range filter
+    (45, 61, 6, 0.1, 2.0, math.inf, 3),       # pure spatial (normalised conv)
+    (45, 61, 6, 0.1, math.inf, math.inf, 3),  # box average
+    (50, 66, 5, 0.08, 0.25, 0.25, 8),         # smallest sigmas: heavy rescale
+    (50, 66, 9, 0.03, 3.0, 2.0, 8),           # far colours: underflow-prone
+    (129, 257, 16, 0.06, 5.0, 14.0, 7),       # radius at the template edge
+    (129, 257, 17, 0.06, 5.0, 14.0, 7),       # first radius of the big table
+]
+
+
+@pytest.mark.parametrize("case", FILTER_CASES,
+                         ids=[f"{c[0]}x{c[1]}r{c[2]}" for c in FILTER_CASES])
+def test_filter_random(torch_dev, case):
+    torch, dev = torch_dev
+    h, w, r, dens, ss, sr, pal = case
+    d, b, rgb = S.tiny_random(np.random.default_rng(hash(case) & 0xFFFF), h, w,
+                              dens, n_colors=pal)
+    check_filter(torch, dev, d, b, rgb, r, ss, sr)
+
+
+def test_filter_ignores_depth_where_invalid(torch_dev):
+    torch, dev = torch_dev
+    d, b, rgb = S.tiny_random(np.random.default_rng(3), 40, 40, 0.1,
+                              n_colors=3)
+    out1, m1 = _gpu_densify(torch, dev, d, b, rgb, 4, 2.0, 12.0)
+    junk = np.where(b == 1, d, np.float32(1e30)).astype(np.float32)
+    out2, m2 = _gpu_densify(torch, dev, junk, b, rgb, 4, 2.0, 12.0)
+    np.testing.assert_array_equal(out1, out2)
+    np.testing.assert_array_equal(m1, m2)
+
+
+def test_filter_constant_power_of_two_depth(torch_dev):
+    """Same weights in numerator and denominator: a constant 2^k depth comes
+    back exactly (scaling by 2^k commutes with rounding)."""
+    torch, dev = torch_dev
+    d, b, rgb = S.tiny_random(np.random.default_rng(4), 70, 90, 0.1,
+                              n_colors=4)
+    d = np.where(b == 1, np.float32(4.0), np.float32(0)).astype(np.float32)
+    out, mask = _gpu_densify(torch, dev, d, b, rgb, 6, 3.0, 12.0)
+    assert np.all(out[mask == 1] == 4.0)
+
+
+def test_filter_deterministic(torch_dev):
+    torch, dev = torch_dev
+    f = S.small_view(S.seeded(1))
+    cam = f.camera
+    _, depth, valid, _ = oracle.project(f.points, cam.pose, cam.intrinsics(),
+                                        cam.width, cam.height)
+    a = _gpu_densify(torch, dev, depth, valid, f.rgb, 5, 3.0, 12.0)
+    b = _gpu_densify(torch, dev, depth, valid, f.rgb, 5, 3.0, 12.0)
+    np.testing.assert_array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+
+
+@pytest.mark.parametrize("cfg", ["small", "fullhd"])
+def test_pipeline_scene(torch_dev, cfg):
+    """project -> densify on the GPU vs the oracle on the whole frame."""
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import densify, project
+    f = S.small_view(S.seeded(1)) if cfg == "small" else \
+        S.fullhd_view(S.seeded(2))
+    cam = f.camera
+    print("pipeline", cfg, cam.width, cam.height, len(f.points), flush=True)
+    _, depth, valid, _ = oracle.project(f.points, cam.pose, cam.intrinsics(),
+                                        cam.width, cam.height)
+    ref, rmask = oracle.densify(depth, valid, f.rgb, f.radius, f.sigma_s,
+                                f.sigma_r)
+    pts = torch.from_numpy(f.points).to(dev)
+    zbuf, gd, gv = project(pts, cam.pose, cam.intrinsics(), cam.width,
+                           cam.height)
+    rgb = torch.from_numpy(f.rgb).to(dev)
+    out, mask = densify(gd, gv, rgb, f.radius, f.sigma_s, f.sigma_r)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    mask = mask.cpu().numpy()
+    np.testing.assert_array_equal(mask, rmask)
+    sel = mask == 1
+    rel = np.abs(out[sel] - ref[sel]) / ref[sel]
+    print(f"  valid={int(sel.sum())} max_rel={rel.max():.3e} "
+          f"mean_rel={rel.mean():.3e}", flush=True)
+    assert rel.max() <= REL_TOL
+    assert np.all(out[~sel] == 0)
