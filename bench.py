@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=512,
+                    help="size of the plain device copy that calibrates the "
+                         "HBM byte counters and gives the copy ceiling")
     return ap.parse_args()
 
 
@@ -167,6 +170,29 @@ def main():
                 "kernel": "k_jbf_fwd_f32", "pairs_per_launch": pairs,
                 "flops_per_pair": FLOPS_PER_PAIR}
 
+    # plain device-to-device copy of known size: the measured HBM ceiling,
+    # and the reference dispatch for scaling FETCH_SIZE / WRITE_SIZE
+    copy = None
+    if args.copy_mb > 0:
+        nb = args.copy_mb << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+        src.fill_(1)
+        dst.copy_(src)
+        ce = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        reps = 5
+        ce[0].record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        ce[1].record(stream)
+        torch.cuda.synchronize()
+        t_copy = ce[0].elapsed_time(ce[1]) / reps * 1e-3
+        copy = {"bytes_moved": 2 * nb,
+                "gbs": round(2 * nb / t_copy / 1e9, 1),
+                "frac_of_hbm_peak": round(2 * nb / t_copy / 1e9 / HBM_PEAK_GBS, 3)}
+        del src, dst
+
     # plain per-frame end-to-end path: pinned upload, project, filter,
     # pinned download, synchronise, one frame at a time
     pts_pin = pts_h.pin_memory()
@@ -175,7 +201,7 @@ def main():
     m_pin = torch.empty((H, W), dtype=torch.uint8).pin_memory()
     b = sets[0]
     lat = []
-    for k in range(args.e2e_frames + 5):
+    for k in range(args.e2e_frames + 5 if args.e2e_frames > 0 else 0):
         t = time.perf_counter()
         b["pts"].copy_(pts_pin, non_blocking=True)
         b["rgb"].copy_(rgb_pin, non_blocking=True)
@@ -185,7 +211,7 @@ def main():
         torch.cuda.synchronize()
         if k >= 5:
             lat.append((time.perf_counter() - t) * 1e3)
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.array([np.nan])
     e2e = {"frames_per_s": round(1e3 / float(lat.mean()), 1),
            "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -227,7 +253,8 @@ def main():
                       "k_jbf_fwd_f32": round(float(filt_ms.mean()), 4),
                       "k_jbf_fwd_f32_p99": round(float(np.percentile(filt_ms, 99)), 4)},
         "roofline": roofline,
-        "plain_e2e": e2e,
+        "plain_e2e": e2e if args.e2e_frames > 0 else None,
+        "device_copy": copy,
         "cpu_baseline": cpu,
         "generator_s": round(t_gen, 2),
     }

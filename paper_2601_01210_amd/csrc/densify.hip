@@ -10,7 +10,9 @@
 //
 //   1. Each wave streams the halo of its block ((8+2r)^2 pixels, clipped) in
 //      chunks of 64 pixels, one per lane, and compacts the valid ones with a
-//      ballot into a wave-private LDS list: 16-byte records
+//      ballot into a wave-private LDS list. The stream is software-pipelined:
+//      the mask bytes of chunk c+2 and the sample data of chunk c+1 are
+//      loaded while chunk c is processed. Records are 16 bytes
 //      {halo xy (u16x2), (r,g) as f16x2, (b,0) as f16x2, depth (f32)} plus
 //      -|rgb|^2/2 (f32) in a parallel array.
 //   2. The wave then walks that list in lockstep: every lane (one output
@@ -156,7 +158,6 @@ __global__ __launch_bounds__(256) void k_jbf_fwd_f32(
     const int hw = hx1 - hx0;          // >= 1: the block holds a pixel
     const int npx = hw * (hy1 - hy0);
     const int step_x = 64 % hw, step_y = 64 / hw;
-    int cx = lane % hw, cy = lane / hw;
 
     Rec *my = recs[wid];
     float *myq = nq2h[wid];
@@ -165,35 +166,130 @@ __global__ __launch_bounds__(256) void k_jbf_fwd_f32(
     float num = 0.0f, den = 0.0f;
     const unsigned char *Gb = reinterpret_cast<const unsigned char *>(G);
 
-    for (int base = 0; base < npx; base += 64) {
-        const int sx = hx0 + cx, sy = hy0 + cy;
-        bool v = false;
-        int64_t sp = 0;
-        if (base + lane < npx) {
-            sp = (int64_t)sy * W + sx;
-            v = B[sp] != 0;
-        }
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(v);
-        if (v) {
-            Rec rec;
-            float q2;
-            load_rgb(rgb, sp, rec.rg, rec.b0, q2);
-            rec.xy = (uint32_t)(sx - (bx - r)) | ((uint32_t)(sy - (by - r)) << 16);
-            rec.d = D[sp];
-            const int pos = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            my[pos] = rec;
-            myq[pos] = -0.5f * q2;
-        }
+    // Software pipeline over 64-pixel halo chunks: while the samples of
+    // chunk c are processed from LDS, the sample loads of chunk c+1 and the
+    // mask loads of chunk c+2 are in flight. Loaded values are only consumed
+    // after the compute loop, so no wait is forced before it.
+    int cx = lane % hw, cy = lane / hw;          // this lane's pixel, chunk 0
+    auto advance = [&]() {
         cx += step_x;
         cy += step_y;
         if (cx >= hw) {
             cx -= hw;
             cy += 1;
         }
-        const int cnt = __builtin_popcountll(bal);
+    };
+    // pixel index of this lane in the current chunk (clamped to the first
+    // halo pixel past the end, so the mask load is always in bounds)
+    auto pix = [&](int base) -> uint32_t {
+        const bool in = base + lane < npx;
+        return in ? (uint32_t)(hy0 + cy) * (uint32_t)W + (uint32_t)(hx0 + cx)
+                  : (uint32_t)hy0 * (uint32_t)W + (uint32_t)hx0;
+    };
+    auto xy_of = [&]() -> uint32_t {
+        return (uint32_t)(hx0 + cx - (bx - r)) | ((uint32_t)(hy0 + cy - (by - r)) << 16);
+    };
+    auto stage = [&](bool v, uint64_t bal, uint32_t xy, uint32_t c01,
+                     uint32_t c2, float d) {
+        if (v) {
+            const float fr = (float)(c01 & 255u), fg = (float)(c01 >> 8),
+                        fb = (float)c2;
+            h2 a = {(_Float16)fr, (_Float16)fg};
+            h2 c = {(_Float16)fb, (_Float16)0.0f};
+            Rec rec;
+            rec.xy = xy;
+            rec.rg = __builtin_bit_cast(uint32_t, a);
+            rec.b0 = __builtin_bit_cast(uint32_t, c);
+            rec.d = d;
+            const int pos = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            my[pos] = rec;
+            myq[pos] = -0.5f * (fr * fr + fg * fg + fb * fb);
+        }
+    };
+
+    // prologue: chunk 0 fully staged, chunk 1 mask in flight
+    uint32_t p0 = pix(0);
+    bool v0 = (B[p0] != 0) && (lane < npx);
+    uint64_t bal0 = __builtin_amdgcn_ballot_w64(v0);
+    {
+        uint32_t c01 = 0, c2 = 0;
+        float d = 0.0f;
+        if (v0) {
+            const uint8_t *c = rgb + 3 * (int64_t)p0;
+            c01 = (uint32_t)c[0] | ((uint32_t)c[1] << 8);
+            c2 = c[2];
+            d = D[p0];
+        }
+        stage(v0, bal0, xy_of(), c01, c2, d);
+    }
+    advance();
+    uint32_t p1 = pix(64);
+    uint32_t m1 = B[p1];
+    int cnt = __builtin_popcountll(bal0);
+
+    for (int base = 0; base < npx; base += 64) {
+        // chunk c+1: its mask arrived during the previous compute loop
+        const bool v1 = (m1 != 0u) && (base + 64 + lane < npx);
+        const uint64_t bal1 = __builtin_amdgcn_ballot_w64(v1);
+        const uint32_t xy1 = xy_of();
+        uint32_t c01 = 0, c2 = 0;
+        float d1 = 0.0f;
+        if (v1) {
+            const uint8_t *c = rgb + 3 * (int64_t)p1;
+            c01 = (uint32_t)c[0] | ((uint32_t)c[1] << 8);
+            c2 = c[2];
+            d1 = D[p1];
+        }
+        // chunk c+2: mask load
+        advance();
+        const uint32_t p2n = pix(base + 128);
+        const uint32_t m2 = B[p2n];
         __builtin_amdgcn_wave_barrier();
-        for (int s = 0; s < cnt; ++s) {
+        // groups of four samples: all LDS reads first, one range test, and
+        // the rescale path only when an exponent of the group exceeds +12
+        int s = 0;
+        for (; s + 4 <= cnt; s += 4) {
+            float t[4], g[4], d[4], a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const Rec q = my[s + u];
+                t[u] = dot2h(prg, q.rg, dot2h(pb0, q.b0, myq[s + u]));
+                const uint32_t gaddr = dot2_u16(pk_sub_u16(lxy, q.xy), gstride, 0u);
+                g[u] = *reinterpret_cast<const float *>(Gb + gaddr);
+                d[u] = q.d;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = __builtin_fmaf(kr2, t[u], M) + g[u];
+            const float amax = fmaxf(fmaxf(a[0], a[1]), fmaxf(a[2], a[3]));
+            if (amax > kRescaleAbove) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float au = __builtin_fmaf(kr2, t[u], M) + g[u];
+                    if (au > kRescaleAbove) {
+                        const float k = __builtin_ceilf(au);
+                        const int ki = (int)k;
+                        num = __builtin_ldexpf(num, -ki);
+                        den = __builtin_ldexpf(den, -ki);
+                        M -= k;
+                        au = __builtin_fmaf(kr2, t[u], M) + g[u];
+                    }
+                    a[u] = au;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // M may have dropped after a[u] was formed: re-form it
+                    a[u] = __builtin_fmaf(kr2, t[u], M) + g[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float w = __builtin_amdgcn_exp2f(a[u]);
+                num = __builtin_fmaf(w, d[u], num);
+                den += w;
+            }
+        }
+        for (; s < cnt; ++s) {
             const Rec q = my[s];
             const float t = dot2h(prg, q.rg, dot2h(pb0, q.b0, myq[s]));
             const uint32_t gaddr = dot2_u16(pk_sub_u16(lxy, q.xy), gstride, 0u);
@@ -212,6 +308,10 @@ __global__ __launch_bounds__(256) void k_jbf_fwd_f32(
             den += w;
         }
         __builtin_amdgcn_wave_barrier();
+        stage(v1, bal1, xy1, c01, c2, d1);
+        cnt = __builtin_popcountll(bal1);
+        p1 = p2n;
+        m1 = m2;
     }
 
     if (inside) {
