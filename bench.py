@@ -2,8 +2,9 @@
 
 One step = the whole hot path on one synthetic Full-HD viewpoint whose
 inputs are already resident in HBM: projection of the ~2e5 merged points of
-three staggered 32-beam sweeps (clear + project + decode) followed by the
-r = 15, sigma_s = 6, sigma_r = 15 joint bilateral filter. Input and output
+three staggered 32-beam sweeps (clear + project + decode), the per-strip
+sample lists, and the r = 15, sigma_s = 6, sigma_r = 15 joint bilateral
+filter. Input and output
 buffers rotate over enough distinct copies (> 512 MB) that the 256 MB
 Infinity Cache cannot hold them.
 
@@ -97,7 +98,8 @@ def main():
 
     import torch
 
-    from paper_2601_01210_amd import densify, project
+    from paper_2601_01210_amd import (densify, densify_prepare,
+                                      densify_workspace, project)
     from synth import scenes as S
 
     dev = torch.device("cuda:0")
@@ -111,7 +113,8 @@ def main():
     n_pts = len(frame.points)
 
     # rotating device buffers
-    per_set = (n_pts * 12 + H * W * 3 + H * W * 8 + H * W * 5 + H * W * 5)
+    per_set = (n_pts * 12 + H * W * 3 + H * W * 8 + H * W * 5 + H * W * 5 +
+               n_pts * 5 * 20)
     n_sets = max(2, math.ceil(ROTATE_BYTES / per_set))
     pts_h = torch.from_numpy(frame.points)
     rgb_h = torch.from_numpy(frame.rgb)
@@ -123,7 +126,9 @@ def main():
             d=torch.empty((H, W), dtype=torch.float32, device=dev),
             v=torch.empty((H, W), dtype=torch.uint8, device=dev),
             out=torch.empty((H, W), dtype=torch.float32, device=dev),
-            m=torch.empty((H, W), dtype=torch.uint8, device=dev)))
+            m=torch.empty((H, W), dtype=torch.uint8, device=dev),
+            # sample-list workspace: the point count bounds the valid pixels
+            ws=densify_workspace(H, W, r, n_pts, dev)))
     stream = torch.cuda.current_stream(dev)
 
     def step(b, ev=None):
@@ -133,10 +138,13 @@ def main():
                 depth=b["d"], valid=b["v"])
         if ev is not None:
             ev[1].record(stream)
-        densify(b["d"], b["v"], b["rgb"], r, ss, sr, out=b["out"],
-                mask=b["m"])
+        densify_prepare(b["d"], b["v"], b["rgb"], r, b["ws"])
         if ev is not None:
             ev[2].record(stream)
+        densify(b["d"], b["v"], b["rgb"], r, ss, sr, out=b["out"],
+                mask=b["m"], ws=b["ws"], lists_ready=True)
+        if ev is not None:
+            ev[3].record(stream)
 
     for k in range(args.warmup):
         step(sets[k % n_sets])
@@ -146,18 +154,28 @@ def main():
     n_valid = int(valid_np.sum())
     pairs = window_pairs(valid_np, r)
 
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
-              for _ in range(args.steps)]
+    # throughput: K steps back to back, no events between kernels (an event
+    # recorded between two kernels idles the GPU for a few microseconds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(sets[k % n_sets], events[k])
+        step(sets[k % n_sets])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    proj_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
-    filt_ms = np.array([e[1].elapsed_time(e[2]) for e in events])
     step_ms = wall * 1e3 / args.steps
     fps = args.steps / wall
+
+    # per-kernel durations: a second pass with HIP events recorded on the
+    # launch stream around each stage
+    n_ev = max(args.steps // 2, 10)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)]
+              for _ in range(n_ev)]
+    for k in range(n_ev):
+        step(sets[k % n_sets], events[k])
+    torch.cuda.synchronize()
+    proj_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
+    list_ms = np.array([e[1].elapsed_time(e[2]) for e in events])
+    filt_ms = np.array([e[2].elapsed_time(e[3]) for e in events])
 
     # roofline of the filter kernel (the dominant kernel)
     t_filt = float(filt_ms.mean()) * 1e-3
@@ -250,6 +268,7 @@ def main():
                    "points": n_pts, "valid_pixels": n_valid,
                    "seed": args.seed, "buffer_sets": n_sets},
         "kernel_ms": {"project": round(float(proj_ms.mean()), 4),
+                      "sample_lists": round(float(list_ms.mean()), 4),
                       "k_jbf_fwd_f32": round(float(filt_ms.mean()), 4),
                       "k_jbf_fwd_f32_p99": round(float(np.percentile(filt_ms, 99)), 4)},
         "roofline": roofline,

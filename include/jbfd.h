@@ -60,6 +60,10 @@ extern "C" {
  * per-workgroup spatial table in LDS. */
 #define JBFD_MAX_RADIUS 32
 
+/* Largest image width or height (pixel coordinates plus the halo travel as
+ * packed 16-bit values inside the kernels). */
+#define JBFD_MAX_SIDE 32767
+
 /* Smallest accepted sigma (pixels for sigma_s, RGB units for sigma_r). Below
  * it the log2-domain weight exponent of a far sample would exceed the range
  * in which the FP32 kernels keep it exact. */
@@ -79,13 +83,18 @@ typedef enum jbfd_precision {
                              spatial weight, depth, sums, divide in FP32 */
 } jbfd_precision;
 
+/* Flags of jbfd_densify. */
+#define JBFD_LISTS_READY 1u  /* ws already holds the sample lists of these
+                                inputs (from jbfd_densify_prepare): skip
+                                building them */
+
 /* Pinhole intrinsics of a camera and the size of its image. */
 typedef struct jbfd_intrinsics {
     double fx, fy;        /* focal lengths in pixels */
     double cx, cy;        /* principal point, pixel-edge convention
                              (a centred camera has cx = W/2) */
-    int32_t width;        /* W, 1 .. 65535 */
-    int32_t height;       /* H, 1 .. 65535 */
+    int32_t width;        /* W, 1 .. JBFD_MAX_SIDE */
+    int32_t height;       /* H, 1 .. JBFD_MAX_SIDE */
 } jbfd_intrinsics;
 
 /* Version of this interface (JBFD_ABI_VERSION of the built library). */
@@ -147,7 +156,7 @@ jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
  *
  * sparse_depth, sparse_valid  H*W float32 / uint8 (device)
  * rgb_hwc         H*W*3 uint8 guide image (device)
- * H, W            1 .. 65535 each
+ * H, W            1 .. JBFD_MAX_SIDE each
  * radius          0 .. JBFD_MAX_RADIUS
  * sigma_s         spatial width in pixels, >= JBFD_MIN_SIGMA or +inf
  * sigma_r         colour width in RGB units, >= JBFD_MIN_SIGMA or +inf
@@ -155,14 +164,43 @@ jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
  * dense_depth     H*W float32 output (device)
  * dense_valid     H*W uint8 output (device)
  * aux             NULL, or H*W*2 float32 output (device) saved for
- *                 jbfd_densify_backward: per pixel the integer log2 shift
- *                 and the shifted weight sum (FP32 precision only)
+ *                 jbfd_densify_backward: per pixel the log2 shift of its
+ *                 weights and the shifted weight sum (FP32 precision only)
+ * ws, ws_bytes    NULL/0, or a device workspace (256-byte aligned). With at
+ *                 least jbfd_densify_ws_bytes(H, W, radius, n) bytes, where
+ *                 n bounds the number of valid samples (the number of
+ *                 projected points is such a bound), the call first builds
+ *                 per-strip sample lists and the filter reads them; with a
+ *                 smaller or no workspace, or if the image holds more valid
+ *                 samples than the workspace can list, the filter streams
+ *                 the inputs directly. Both ways visit the samples in the
+ *                 same (row-major) order; they may differ in the last bits
+ *                 where a range rescale falls inside a group of samples.
  */
 jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,
                          const uint8_t *rgb_hwc, int32_t H, int32_t W,
                          int32_t radius, float sigma_s, float sigma_r,
                          jbfd_precision prec, float *dense_depth,
-                         uint8_t *dense_valid, float *aux, void *stream);
+                         uint8_t *dense_valid, float *aux, void *ws,
+                         size_t ws_bytes, uint32_t flags, void *stream);
+
+/*
+ * Build jbfd_densify's per-strip sample lists in ws (the first half of a
+ * jbfd_densify call with a workspace). A following jbfd_densify (or
+ * jbfd_densify_backward) on the same inputs, radius and workspace may pass
+ * JBFD_LISTS_READY to reuse them. ws must not be NULL; a workspace smaller
+ * than needed leaves lists the filter will not use (it streams instead).
+ */
+jbfd_status jbfd_densify_prepare(const float *sparse_depth,
+                                 const uint8_t *sparse_valid,
+                                 const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                                 int32_t radius, void *ws, size_t ws_bytes,
+                                 void *stream);
+
+/* Workspace bytes for jbfd_densify's sample lists on an H x W image with
+ * at most max_samples valid samples; 0 for invalid sizes. */
+size_t jbfd_densify_ws_bytes(int32_t H, int32_t W, int32_t radius,
+                             int64_t max_samples);
 
 /*
  * Gradient of a scalar loss L through jbfd_densify (FP32 precision).

@@ -8,4 +8,6 @@ HIP kernels. There is no CPU fallback: if libjbfd.so is missing the calls
 raise.
 """
 from .binding import (JbfdError, Precision, abi_version, densify,  # noqa: F401
-                      densify_backward, library_path, project)
+                      densify_backward, densify_prepare, densify_workspace,
+                      densify_ws_bytes,
+                      library_path, project)

@@ -64,7 +64,13 @@ def lib():
                                    C.POINTER(Intrinsics), vp, vp, vp, vp]
         L.jbfd_densify.restype = C.c_int
         L.jbfd_densify.argtypes = [vp, vp, vp, i32, i32, i32, f32, f32,
-                                   C.c_int, vp, vp, vp, vp]
+                                   C.c_int, vp, vp, vp, vp, sz, C.c_uint32,
+                                   vp]
+        L.jbfd_densify_prepare.restype = C.c_int
+        L.jbfd_densify_prepare.argtypes = [vp, vp, vp, i32, i32, i32, vp, sz,
+                                           vp]
+        L.jbfd_densify_ws_bytes.restype = sz
+        L.jbfd_densify_ws_bytes.argtypes = [i32, i32, i32, i64]
         L.jbfd_densify_backward.restype = C.c_int
         L.jbfd_densify_backward.argtypes = [vp, vp, vp, i32, i32, i32, f32,
                                             f32, vp, vp, vp, vp, vp, vp, sz,
@@ -154,13 +160,29 @@ def project(points, pose, intrinsics: Sequence[float], width: int,
     return zbuf, depth, valid
 
 
+def densify_ws_bytes(h: int, w: int, radius: int, max_samples: int) -> int:
+    return int(lib().jbfd_densify_ws_bytes(h, w, radius, max_samples))
+
+
+def densify_workspace(h: int, w: int, radius: int, max_samples: int,
+                      device=None):
+    """Device workspace for jbfd_densify's sample lists (uint8 tensor)."""
+    torch = _torch()
+    n = densify_ws_bytes(h, w, radius, max_samples)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
 def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
             precision: Precision = Precision.FP32, out=None, mask=None,
-            aux=None, want_aux: bool = False):
+            aux=None, want_aux: bool = False, ws="auto",
+            max_samples: Optional[int] = None, lists_ready: bool = False):
     """Joint bilateral filter (jbfd_densify).
 
     depth (H,W) float32, valid (H,W) uint8, rgb (H,W,3) uint8, all on the
-    device. Returns (dense depth float32, mask uint8[, aux float32 (H,W,2)]).
+    device. ``ws`` is a workspace tensor from :func:`densify_workspace`,
+    ``None`` (filter streams the inputs directly) or "auto" (allocate one
+    sized for ``max_samples`` valid samples, default H*W/4).
+    Returns (dense depth float32, mask uint8[, aux float32 (H,W,2)]).
     """
     torch = _torch()
     _need(depth, torch.float32, None, "depth")
@@ -180,13 +202,36 @@ def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
         aux = torch.empty((h, w, 2), dtype=torch.float32, device=dev)
     if aux is not None:
         _need(aux, torch.float32, (h, w, 2), "aux")
+    if isinstance(ws, str):
+        if ws != "auto":
+            raise ValueError("ws must be a tensor, None or 'auto'")
+        ms = max_samples if max_samples is not None else (h * w) // 4
+        ws = densify_workspace(h, w, radius, ms, dev)
+    if ws is not None:
+        _need(ws, torch.uint8, None, "ws")
     _check(lib().jbfd_densify(_ptr(depth), _ptr(valid), _ptr(rgb), h, w,
                               int(radius), float(sigma_s), float(sigma_r),
                               int(precision), _ptr(out), _ptr(mask),
-                              _ptr(aux), _stream(dev)))
+                              _ptr(aux), _ptr(ws),
+                              ws.numel() if ws is not None else 0,
+                              1 if lists_ready else 0, _stream(dev)))
     if aux is not None:
         return out, mask, aux
     return out, mask
+
+
+def densify_prepare(depth, valid, rgb, radius: int, ws):
+    """Build the per-strip sample lists of jbfd_densify in ``ws``."""
+    torch = _torch()
+    h, w = depth.shape
+    _need(depth, torch.float32, (h, w), "depth")
+    _need(valid, torch.uint8, (h, w), "valid")
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    _need(ws, torch.uint8, None, "ws")
+    _check(lib().jbfd_densify_prepare(_ptr(depth), _ptr(valid), _ptr(rgb), h,
+                                      w, int(radius), _ptr(ws), ws.numel(),
+                                      _stream(depth.device)))
+    return ws
 
 
 def densify_backward(depth, valid, rgb, radius: int, sigma_s: float,

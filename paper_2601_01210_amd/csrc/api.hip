@@ -44,8 +44,9 @@ float log2_half_inv_var(float sigma) {
 }
 
 jbfd_status check_image(int32_t H, int32_t W) {
-    if (H <= 0 || W <= 0 || H > 65535 || W > 65535)
-        return fail(JBFD_EINVAL, "image size %d x %d outside 1..65535", H, W);
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE)
+        return fail(JBFD_EINVAL, "image size %d x %d outside 1..%d", H, W,
+                    JBFD_MAX_SIDE);
     return JBFD_OK;
 }
 
@@ -113,7 +114,8 @@ jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,
                          const uint8_t *rgb_hwc, int32_t H, int32_t W,
                          int32_t radius, float sigma_s, float sigma_r,
                          jbfd_precision prec, float *dense_depth,
-                         uint8_t *dense_valid, float *aux, void *stream) {
+                         uint8_t *dense_valid, float *aux, void *ws,
+                         size_t ws_bytes, uint32_t flags, void *stream) {
     if (!sparse_depth || !sparse_valid || !rgb_hwc || !dense_depth || !dense_valid)
         return fail(JBFD_EINVAL, "jbfd_densify: null buffer");
     jbfd_status st = check_image(H, W);
@@ -124,14 +126,40 @@ jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,
         return fail(JBFD_EINVAL, "jbfd_densify: unknown precision %d", (int)prec);
     if (aux && prec != JBFD_FP32)
         return fail(JBFD_EINVAL, "jbfd_densify: aux is produced by FP32 only");
+    if (ws && ((uintptr_t)ws & 255))
+        return fail(JBFD_EINVAL, "jbfd_densify: workspace not 256-byte aligned");
+    if (!ws) ws_bytes = 0;
+    if (flags & ~JBFD_LISTS_READY)
+        return fail(JBFD_EINVAL, "jbfd_densify: unknown flags 0x%x", flags);
     jbfd::FilterParams fp{radius, log2_half_inv_var(sigma_r),
                           log2_half_inv_var(sigma_s)};
     hipError_t e = jbfd::launch_densify(sparse_depth, sparse_valid, rgb_hwc, H, W,
                                         fp, prec, dense_depth, dense_valid, aux,
+                                        ws, ws_bytes, (flags & JBFD_LISTS_READY) != 0,
                                         (hipStream_t)stream);
     if (e == hipErrorNotSupported)
         return fail(JBFD_EUNSUPPORTED, "jbfd_densify: precision not built");
     return hip_status(e, "jbfd_densify");
+}
+
+jbfd_status jbfd_densify_prepare(const float *sparse_depth,
+                                 const uint8_t *sparse_valid,
+                                 const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                                 int32_t radius, void *ws, size_t ws_bytes,
+                                 void *stream) {
+    if (!sparse_depth || !sparse_valid || !rgb_hwc || !ws)
+        return fail(JBFD_EINVAL, "jbfd_densify_prepare: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    if (radius < 0 || radius > JBFD_MAX_RADIUS)
+        return fail(JBFD_EINVAL, "radius %d outside 0..%d", radius,
+                    JBFD_MAX_RADIUS);
+    if ((uintptr_t)ws & 255)
+        return fail(JBFD_EINVAL, "jbfd_densify_prepare: workspace not aligned");
+    return hip_status(jbfd::launch_densify_prepare(sparse_depth, sparse_valid,
+                                                   rgb_hwc, H, W, radius, ws,
+                                                   ws_bytes, (hipStream_t)stream),
+                      "jbfd_densify_prepare");
 }
 
 jbfd_status jbfd_densify_backward(const float *sparse_depth,
@@ -159,6 +187,14 @@ jbfd_status jbfd_densify_backward(const float *sparse_depth,
                           sigma_r, dense_depth, aux, grad_out, grad_depth,
                           grad_sigmas, ws, (hipStream_t)stream),
                       "jbfd_densify_backward");
+}
+
+size_t jbfd_densify_ws_bytes(int32_t H, int32_t W, int32_t radius,
+                             int64_t max_samples) {
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE || radius < 0 ||
+        radius > JBFD_MAX_RADIUS || max_samples < 0)
+        return 0;
+    return jbfd::densify_ws_bytes(H, W, radius, max_samples);
 }
 
 size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W) {

@@ -36,7 +36,15 @@ hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
 hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                           int32_t H, int32_t W, const FilterParams &fp,
                           jbfd_precision prec, float *out, uint8_t *mask,
-                          float *aux, hipStream_t s);
+                          float *aux, void *ws, size_t ws_bytes, bool lists_ready,
+                          hipStream_t s);
+
+hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
+                                  const uint8_t *rgb, int32_t H, int32_t W,
+                                  int32_t radius, void *ws, size_t ws_bytes,
+                                  hipStream_t s);
+
+size_t densify_ws_bytes(int32_t H, int32_t W, int32_t r, int64_t max_samples);
 
 hipError_t launch_densify_backward(const float *D, const uint8_t *B,
                                    const uint8_t *rgb, int32_t H, int32_t W,

@@ -82,24 +82,43 @@ def test_densify_rejects_bad_filter(L, radius, ss, sr):
     from paper_2601_01210_amd.binding import JBFD_EINVAL
     f = C.c_void_p(0x1000)
     st = L.jbfd_densify(f, f, f, 10, 10, radius, C.c_float(ss), C.c_float(sr),
-                        0, f, f, None, None)
+                        0, f, f, None, None, 0, 0, None)
     assert st == JBFD_EINVAL
 
 
 def test_densify_rejects_sizes_and_nulls(L):
     from paper_2601_01210_amd.binding import JBFD_EINVAL
     f = C.c_void_p(0x1000)
-    assert L.jbfd_densify(f, f, f, 0, 10, 2, C.c_float(1), C.c_float(1), 0,
-                          f, f, None, None) == JBFD_EINVAL
-    assert L.jbfd_densify(f, f, f, 10, 70000, 2, C.c_float(1), C.c_float(1),
-                          0, f, f, None, None) == JBFD_EINVAL
-    assert L.jbfd_densify(None, f, f, 10, 10, 2, C.c_float(1), C.c_float(1),
-                          0, f, f, None, None) == JBFD_EINVAL
-    assert L.jbfd_densify(f, f, f, 10, 10, 2, C.c_float(1), C.c_float(1), 7,
-                          f, f, None, None) == JBFD_EINVAL
+    args = (C.c_float(1), C.c_float(1))
+    assert L.jbfd_densify(f, f, f, 0, 10, 2, *args, 0, f, f, None, None, 0, 0,
+                          None) == JBFD_EINVAL
+    assert L.jbfd_densify(f, f, f, 10, 32768, 2, *args, 0, f, f, None, None,
+                          0, 0, None) == JBFD_EINVAL
+    assert L.jbfd_densify(None, f, f, 10, 10, 2, *args, 0, f, f, None, None,
+                          0, 0, None) == JBFD_EINVAL
+    assert L.jbfd_densify(f, f, f, 10, 10, 2, *args, 7, f, f, None, None, 0, 0,
+                          None) == JBFD_EINVAL
     # aux is an FP32-only output
-    assert L.jbfd_densify(f, f, f, 10, 10, 2, C.c_float(1), C.c_float(1), 1,
-                          f, f, f, None) == JBFD_EINVAL
+    assert L.jbfd_densify(f, f, f, 10, 10, 2, *args, 1, f, f, f, None, 0, 0,
+                          None) == JBFD_EINVAL
+    # the workspace must be 256-byte aligned
+    assert L.jbfd_densify(f, f, f, 10, 10, 2, *args, 0, f, f, None,
+                          C.c_void_p(0x1010), 4096, 0, None) == JBFD_EINVAL
+    assert b"aligned" in L.jbfd_last_error()
+    assert L.jbfd_densify(f, f, f, 10, 10, 2, *args, 0, f, f, None, None, 0,
+                          8, None) == JBFD_EINVAL
+    assert L.jbfd_densify_prepare(f, f, f, 10, 10, 2, None, 0,
+                                  None) == JBFD_EINVAL
+
+
+def test_densify_ws_bytes(L):
+    a = L.jbfd_densify_ws_bytes(1080, 1920, 15, 0)
+    b = L.jbfd_densify_ws_bytes(1080, 1920, 15, 1000)
+    assert a > 0 and b - a == 1000 * 5 * 20   # 5 strips per column at r=15
+    assert L.jbfd_densify_ws_bytes(1080, 1920, 5, 1000) - \
+        L.jbfd_densify_ws_bytes(1080, 1920, 5, 0) == 1000 * 3 * 20
+    assert L.jbfd_densify_ws_bytes(0, 10, 5, 10) == 0
+    assert L.jbfd_densify_ws_bytes(10, 10, 33, 10) == 0
 
 
 def test_backward_workspace_checks(L):

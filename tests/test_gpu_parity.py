@@ -132,19 +132,25 @@ def test_project_scenes(torch_dev):
 # ---------------------------------------------------------------------------
 
 
-def _gpu_densify(torch, dev, d, b, rgb, r, ss, sr, prec=0):
+def _gpu_densify(torch, dev, d, b, rgb, r, ss, sr, prec=0, ws="auto",
+                 max_samples=None):
     from paper_2601_01210_amd import densify
     td = torch.from_numpy(np.ascontiguousarray(d, np.float32)).to(dev)
     tb = torch.from_numpy(np.ascontiguousarray(b, np.uint8)).to(dev)
     tc = torch.from_numpy(np.ascontiguousarray(rgb, np.uint8)).to(dev)
-    out, mask = densify(td, tb, tc, r, ss, sr, precision=prec)
+    if max_samples is None:
+        max_samples = int(b.sum())
+    out, mask = densify(td, tb, tc, r, ss, sr, precision=prec, ws=ws,
+                        max_samples=max_samples)
     torch.cuda.synchronize()
     return out.cpu().numpy(), mask.cpu().numpy()
 
 
-def check_filter(torch, dev, d, b, rgb, r, ss, sr, tol=REL_TOL):
+def check_filter(torch, dev, d, b, rgb, r, ss, sr, tol=REL_TOL, ws="auto",
+                 max_samples=None):
     ref, rmask = oracle.densify(d, b, rgb, r, ss, sr)
-    out, mask = _gpu_densify(torch, dev, d, b, rgb, r, ss, sr)
+    out, mask = _gpu_densify(torch, dev, d, b, rgb, r, ss, sr, ws=ws,
+                             max_samples=max_samples)
     np.testing.assert_array_equal(mask, rmask)
     sel = mask == 1
     assert np.all(out[~sel] == 0.0)
@@ -178,14 +184,42 @@ FILTER_CASES = [
 ]
 
 
+@pytest.mark.parametrize("path", ["lists", "stream"])
 @pytest.mark.parametrize("case", FILTER_CASES,
                          ids=[f"{c[0]}x{c[1]}r{c[2]}" for c in FILTER_CASES])
-def test_filter_random(torch_dev, case):
+def test_filter_random(torch_dev, case, path):
+    """Both filter paths: per-strip sample lists (workspace sized by the
+    exact sample count) and direct streaming of the inputs (no workspace)."""
     torch, dev = torch_dev
     h, w, r, dens, ss, sr, pal = case
     d, b, rgb = S.tiny_random(np.random.default_rng(hash(case) & 0xFFFF), h, w,
                               dens, n_colors=pal)
-    check_filter(torch, dev, d, b, rgb, r, ss, sr)
+    check_filter(torch, dev, d, b, rgb, r, ss, sr,
+                 ws="auto" if path == "lists" else None)
+
+
+def test_filter_list_overflow_falls_back(torch_dev):
+    """A workspace sized for fewer samples than the image holds: the lists
+    are abandoned on the device and the filter streams the inputs."""
+    torch, dev = torch_dev
+    d, b, rgb = S.tiny_random(np.random.default_rng(9), 90, 120, 0.2,
+                              n_colors=4)
+    check_filter(torch, dev, d, b, rgb, 6, 3.0, 12.0, ws="auto",
+                 max_samples=int(b.sum()) // 3)
+
+
+def test_filter_paths_agree(torch_dev):
+    torch, dev = torch_dev
+    f = S.small_view(S.seeded(1))
+    cam = f.camera
+    _, depth, valid, _ = oracle.project(f.points, cam.pose, cam.intrinsics(),
+                                        cam.width, cam.height)
+    a, ma = _gpu_densify(torch, dev, depth, valid, f.rgb, 5, 3.0, 12.0)
+    b, mb = _gpu_densify(torch, dev, depth, valid, f.rgb, 5, 3.0, 12.0, ws=None)
+    np.testing.assert_array_equal(ma, mb)
+    sel = ma == 1
+    rel = np.abs(a[sel].astype(np.float64) - b[sel]) / b[sel]
+    assert rel.max() <= 2e-6
 
 
 def test_filter_ignores_depth_where_invalid(torch_dev):
@@ -238,7 +272,8 @@ def test_pipeline_scene(torch_dev, cfg):
     zbuf, gd, gv = project(pts, cam.pose, cam.intrinsics(), cam.width,
                            cam.height)
     rgb = torch.from_numpy(f.rgb).to(dev)
-    out, mask = densify(gd, gv, rgb, f.radius, f.sigma_s, f.sigma_r)
+    out, mask = densify(gd, gv, rgb, f.radius, f.sigma_s, f.sigma_r,
+                        max_samples=len(f.points))
     torch.cuda.synchronize()
     out = out.cpu().numpy()
     mask = mask.cpu().numpy()
