@@ -236,6 +236,54 @@ jbfd_status jbfd_densify_backward(const float *sparse_depth,
 /* Workspace bytes needed by jbfd_densify_backward for an H x W image. */
 size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
 
+/*
+ * Batched projection + filter over many viewpoints of mixed image size,
+ * point count and filter parameters (Sec. 2: each viewpoint is processed
+ * on its own, with no exchange between viewpoints).
+ *
+ * Usage: jbfd_batch_prepare() validates the views on the host and writes a
+ * device-side descriptor table into a HOST buffer of
+ * jbfd_batch_table_bytes(n_views) bytes (pinned memory lets the copy be
+ * asynchronous and captured); the caller copies it to device memory and
+ * calls jbfd_batch_run() with that device pointer. jbfd_batch_run launches
+ * fixed-size grids that read every size from the table, so the launches can
+ * be captured once into a HIP graph and replayed for any batch whose table
+ * has at most the captured max_views views and radii <= max_radius.
+ *
+ * Per view, the work is that of jbfd_project followed by jbfd_densify
+ * (without sample lists) on the same definitions; outputs are identical to
+ * the single-view calls. Views must not share output or scratch buffers.
+ */
+typedef struct jbfd_view {
+    const float *points;      /* n_points x 3 float32 world xyz (device) */
+    int64_t n_points;         /* 0 <= n_points < 2^32 */
+    double cam_from_world[12];/* row-major [R|t], finite */
+    jbfd_intrinsics K;        /* camera and image size */
+    const uint8_t *rgb;       /* H*W*3 guide image (device) */
+    int32_t radius;           /* 0 .. JBFD_MAX_RADIUS */
+    float sigma_s, sigma_r;   /* as jbfd_densify */
+    uint64_t *zbuf;           /* H*W scratch (device) */
+    float *sparse_depth;      /* H*W scratch/output (device) */
+    uint8_t *sparse_valid;    /* H*W scratch/output (device) */
+    float *dense_depth;       /* H*W output (device) */
+    uint8_t *dense_valid;     /* H*W output (device) */
+} jbfd_view;
+
+/* Bytes of the descriptor table for n_views views (0 if n_views < 1). */
+size_t jbfd_batch_table_bytes(int32_t n_views);
+
+/* Validate views[0..n_views) (HOST array) and write the descriptor table
+ * into host_table (HOST memory of at least jbfd_batch_table_bytes bytes).
+ * Nothing is enqueued. JBFD_EINVAL names the first bad view. */
+jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
+                               void *host_table, size_t table_bytes);
+
+/* Run a batch whose table (from jbfd_batch_prepare) is at d_table (device,
+ * 8-byte aligned). max_radius bounds every view's radius (it selects the
+ * kernel variant and the LDS size). Capturable in a HIP graph. */
+jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
+                           jbfd_precision prec, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,7 +7,8 @@ and streams) into the C library; every step of the computation runs in the
 HIP kernels. There is no CPU fallback: if libjbfd.so is missing the calls
 raise.
 """
-from .binding import (JbfdError, Precision, abi_version, densify,  # noqa: F401
-                      densify_backward, densify_prepare, densify_workspace,
-                      densify_ws_bytes,
+from .binding import (BatchView, JbfdError, Precision,  # noqa: F401
+                      abi_version, batch_run, batch_table_bytes,
+                      batch_upload, densify, densify_backward,
+                      densify_prepare, densify_workspace, densify_ws_bytes,
                       library_path, project)

@@ -7,6 +7,7 @@ that the C library receives exactly the layouts include/jbfd.h documents.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import enum
 import math
 import os
@@ -35,6 +36,17 @@ class Intrinsics(C.Structure):
     _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double),
                 ("cy", C.c_double), ("width", C.c_int32),
                 ("height", C.c_int32)]
+
+
+class View(C.Structure):
+    """Mirror of jbfd_view (include/jbfd.h)."""
+    _fields_ = [("points", C.c_void_p), ("n_points", C.c_int64),
+                ("cam_from_world", C.c_double * 12), ("K", Intrinsics),
+                ("rgb", C.c_void_p), ("radius", C.c_int32),
+                ("sigma_s", C.c_float), ("sigma_r", C.c_float),
+                ("zbuf", C.c_void_p), ("sparse_depth", C.c_void_p),
+                ("sparse_valid", C.c_void_p), ("dense_depth", C.c_void_p),
+                ("dense_valid", C.c_void_p)]
 
 
 _lib = None
@@ -77,6 +89,12 @@ def lib():
                                             vp]
         L.jbfd_densify_backward_ws_bytes.restype = sz
         L.jbfd_densify_backward_ws_bytes.argtypes = [i32, i32]
+        L.jbfd_batch_table_bytes.restype = sz
+        L.jbfd_batch_table_bytes.argtypes = [i32]
+        L.jbfd_batch_prepare.restype = C.c_int
+        L.jbfd_batch_prepare.argtypes = [C.POINTER(View), i32, vp, sz]
+        L.jbfd_batch_run.restype = C.c_int
+        L.jbfd_batch_run.argtypes = [vp, i32, C.c_int, vp]
         _lib = L
     return _lib
 
@@ -264,3 +282,126 @@ def densify_backward(depth, valid, rgb, radius: int, sigma_s: float,
         _ptr(grad_depth), _ptr(grad_sigmas), _ptr(ws), ws.numel(),
         _stream(dev)))
     return grad_depth, grad_sigmas
+
+
+# ---------------------------------------------------------------------------
+# batches of views (jbfd_batch_prepare / jbfd_batch_run)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class BatchView:
+    """One view of a batch: inputs plus the device buffers the batch writes.
+
+    points (N,3) float32 and rgb (H,W,3) uint8 are device tensors; pose is a
+    3x4 camera-from-world matrix and intrinsics (fx, fy, cx, cy), both host.
+    ``n_points`` may be smaller than ``points.shape[0]`` (a slot buffer
+    sized for the largest frame).
+    """
+    points: object
+    pose: object
+    intrinsics: Tuple[float, float, float, float]
+    width: int
+    height: int
+    rgb: object
+    radius: int
+    sigma_s: float
+    sigma_r: float
+    zbuf: object = None
+    sparse_depth: object = None
+    sparse_valid: object = None
+    dense_depth: object = None
+    dense_valid: object = None
+    n_points: Optional[int] = None
+
+    def allocate(self, device=None):
+        """Allocate any output buffer that is still None."""
+        torch = _torch()
+        dev = device if device is not None else self.points.device
+        hw = (self.height, self.width)
+        if self.zbuf is None:
+            self.zbuf = torch.empty(hw, dtype=torch.int64, device=dev)
+        if self.sparse_depth is None:
+            self.sparse_depth = torch.empty(hw, dtype=torch.float32, device=dev)
+        if self.sparse_valid is None:
+            self.sparse_valid = torch.empty(hw, dtype=torch.uint8, device=dev)
+        if self.dense_depth is None:
+            self.dense_depth = torch.empty(hw, dtype=torch.float32, device=dev)
+        if self.dense_valid is None:
+            self.dense_valid = torch.empty(hw, dtype=torch.uint8, device=dev)
+        return self
+
+    def descriptor(self) -> View:
+        torch = _torch()
+        h, w = self.height, self.width
+        _need(self.points, torch.float32, None, "points")
+        if self.points.dim() != 2 or self.points.shape[1] != 3:
+            raise ValueError("points must have shape (N, 3)")
+        n = self.points.shape[0] if self.n_points is None else int(self.n_points)
+        if not 0 <= n <= self.points.shape[0]:
+            raise ValueError("n_points exceeds the points buffer")
+        _need(self.rgb, torch.uint8, (h, w, 3), "rgb")
+        _need(self.zbuf, torch.int64, (h, w), "zbuf")
+        _need(self.sparse_depth, torch.float32, (h, w), "sparse_depth")
+        _need(self.sparse_valid, torch.uint8, (h, w), "sparse_valid")
+        _need(self.dense_depth, torch.float32, (h, w), "dense_depth")
+        _need(self.dense_valid, torch.uint8, (h, w), "dense_valid")
+        k = self.intrinsics
+        v = View()
+        v.points = self.points.data_ptr()
+        v.n_points = n
+        v.cam_from_world = _pose_array(self.pose)
+        v.K = Intrinsics(float(k[0]), float(k[1]), float(k[2]), float(k[3]),
+                         int(w), int(h))
+        v.rgb = self.rgb.data_ptr()
+        v.radius = int(self.radius)
+        v.sigma_s = float(self.sigma_s)
+        v.sigma_r = float(self.sigma_r)
+        v.zbuf = self.zbuf.data_ptr()
+        v.sparse_depth = self.sparse_depth.data_ptr()
+        v.sparse_valid = self.sparse_valid.data_ptr()
+        v.dense_depth = self.dense_depth.data_ptr()
+        v.dense_valid = self.dense_valid.data_ptr()
+        return v
+
+
+def batch_table_bytes(n_views: int) -> int:
+    return int(lib().jbfd_batch_table_bytes(int(n_views)))
+
+
+def batch_prepare_raw(views: Sequence[View], host) -> None:
+    """jbfd_batch_prepare on plain descriptors into host memory ``host``
+    (a writable buffer: numpy uint8 array or CPU torch uint8 tensor)."""
+    arr = (View * len(views))(*views)
+    if hasattr(host, "data_ptr"):
+        ptr, nbytes = host.data_ptr(), host.numel()
+    else:
+        ptr, nbytes = host.ctypes.data, host.nbytes
+    _check(lib().jbfd_batch_prepare(arr, len(views), C.c_void_p(ptr), nbytes))
+
+
+def batch_upload(views: Sequence[BatchView], table=None, host=None):
+    """Serialise ``views`` and copy the table to the device on the current
+    stream. ``table`` (device uint8) and ``host`` (pinned CPU uint8) are
+    reused when given; the host buffer must not be rewritten until the copy
+    has run (synchronise the stream or alternate two host buffers).
+    Returns (table, host)."""
+    torch = _torch()
+    n = batch_table_bytes(len(views))
+    dev = views[0].points.device
+    if host is None:
+        host = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    if table is None:
+        table = torch.empty(n, dtype=torch.uint8, device=dev)
+    if host.numel() < n or table.numel() < n:
+        raise ValueError(f"batch table needs {n} bytes")
+    batch_prepare_raw([v.descriptor() for v in views], host)
+    table[:n].copy_(host[:n], non_blocking=True)
+    return table, host
+
+
+def batch_run(table, max_radius: int, precision: Precision = Precision.FP32):
+    """Enqueue jbfd_batch_run on the current stream (graph-capturable)."""
+    torch = _torch()
+    _need(table, torch.uint8, None, "table")
+    _check(lib().jbfd_batch_run(_ptr(table), int(max_radius), int(precision),
+                                _stream(table.device)))

@@ -20,6 +20,13 @@ jbfd_status fail(jbfd_status s, const char *fmt, ...) {
     return s;
 }
 
+// Prepend "batch view v: " to the message a check just left.
+jbfd_status prefix_error(jbfd_status s, int32_t v) {
+    char inner[sizeof g_err];
+    snprintf(inner, sizeof inner, "%s", g_err);
+    return fail(s, "batch view %d: %s", v, inner);
+}
+
 jbfd_status ok() {
     g_err[0] = '\0';
     return JBFD_OK;
@@ -200,6 +207,84 @@ size_t jbfd_densify_ws_bytes(int32_t H, int32_t W, int32_t radius,
 size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W) {
     if (H <= 0 || W <= 0) return 0;
     return jbfd::backward_ws_bytes(H, W);
+}
+
+size_t jbfd_batch_table_bytes(int32_t n_views) {
+    if (n_views < 1) return 0;
+    return sizeof(jbfd::BatchHeader) + (size_t)n_views * sizeof(jbfd::BatchView);
+}
+
+jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
+                               void *host_table, size_t table_bytes) {
+    if (!views || !host_table || n_views < 1)
+        return fail(JBFD_EINVAL, "jbfd_batch_prepare: null views/table or no views");
+    if (table_bytes < jbfd_batch_table_bytes(n_views))
+        return fail(JBFD_ENOSPC, "jbfd_batch_prepare: table %zu < %zu bytes",
+                    table_bytes, jbfd_batch_table_bytes(n_views));
+    jbfd::BatchHeader *hdr = static_cast<jbfd::BatchHeader *>(host_table);
+    jbfd::BatchView *out = reinterpret_cast<jbfd::BatchView *>(
+        static_cast<unsigned char *>(host_table) + sizeof(jbfd::BatchHeader));
+    int64_t tiles = 0;
+    for (int32_t v = 0; v < n_views; ++v) {
+        const jbfd_view &x = views[v];
+        if (!x.rgb || !x.zbuf || !x.sparse_depth || !x.sparse_valid ||
+            !x.dense_depth || !x.dense_valid || (x.n_points > 0 && !x.points))
+            return fail(JBFD_EINVAL, "batch view %d: null buffer", v);
+        if (x.n_points < 0 || x.n_points >= ((int64_t)1 << 32))
+            return fail(JBFD_EINVAL, "batch view %d: n_points out of range", v);
+        jbfd_status st = check_image(x.K.height, x.K.width);
+        if (st != JBFD_OK) return prefix_error(st, v);
+        st = check_filter(x.radius, x.sigma_s, x.sigma_r);
+        if (st != JBFD_OK) return prefix_error(st, v);
+        for (int t = 0; t < 12; ++t)
+            if (!isfinite(x.cam_from_world[t]))
+                return fail(JBFD_EINVAL, "batch view %d: pose not finite", v);
+        if (!isfinite(x.K.fx) || !isfinite(x.K.fy) || !isfinite(x.K.cx) ||
+            !isfinite(x.K.cy))
+            return fail(JBFD_EINVAL, "batch view %d: intrinsics not finite", v);
+        jbfd::BatchView &b = out[v];
+        b.pts = x.points;
+        b.n_pts = x.n_points;
+        for (int t = 0; t < 12; ++t) b.pose[t] = x.cam_from_world[t];
+        b.fx = x.K.fx;
+        b.fy = x.K.fy;
+        b.cx = x.K.cx;
+        b.cy = x.K.cy;
+        b.W = x.K.width;
+        b.H = x.K.height;
+        b.rgb = x.rgb;
+        b.zbuf = x.zbuf;
+        b.sd = x.sparse_depth;
+        b.sv = x.sparse_valid;
+        b.out = x.dense_depth;
+        b.mask = x.dense_valid;
+        b.radius = x.radius;
+        b.kr = log2_half_inv_var(x.sigma_r);
+        b.ks = log2_half_inv_var(x.sigma_s);
+        b.tiles_x = (x.K.width + jbfd::kTileEdge - 1) / jbfd::kTileEdge;
+        b.n_tiles = b.tiles_x * ((x.K.height + jbfd::kTileEdge - 1) / jbfd::kTileEdge);
+        b.tile_off = (int32_t)tiles;
+        tiles += b.n_tiles;
+        if (tiles >= ((int64_t)1 << 31))
+            return fail(JBFD_EINVAL, "batch: too many filter tiles");
+    }
+    hdr->n_views = n_views;
+    hdr->total_tiles = (int32_t)tiles;
+    hdr->pad = 0;
+    return ok();
+}
+
+jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
+                           jbfd_precision prec, void *stream) {
+    if (!d_table || ((uintptr_t)d_table & 7))
+        return fail(JBFD_EINVAL, "jbfd_batch_run: null or misaligned table");
+    if (max_radius < 0 || max_radius > JBFD_MAX_RADIUS)
+        return fail(JBFD_EINVAL, "jbfd_batch_run: max_radius %d", max_radius);
+    if (prec != JBFD_FP32 && prec != JBFD_FP16_RANGE)
+        return fail(JBFD_EINVAL, "jbfd_batch_run: unknown precision %d", (int)prec);
+    return hip_status(jbfd::launch_batch(d_table, max_radius, prec,
+                                         (hipStream_t)stream),
+                      "jbfd_batch_run");
 }
 
 }  // extern "C"

@@ -205,29 +205,34 @@ __global__ __launch_bounds__(256) void k_list_scatter(
 // the filter
 // ---------------------------------------------------------------------------
 
-template <int RMAX, int PREC>
-__global__ __launch_bounds__(256) void k_jbf_fwd(
-    const float *__restrict__ D, const uint8_t *__restrict__ B,
-    const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
-    int tiles_x, int n_tiles, int n_pad, ListArgs la, float *__restrict__ out,
-    uint8_t *__restrict__ mask, float2 *__restrict__ aux) {
-    constexpr int kTableMax = (2 * RMAX + 15) * table_stride(RMAX);
-    __shared__ float G[kTableMax];
-    __shared__ Rec recs[kWaves][64];
-    __shared__ float nq2h[kWaves][64];
+// Scratch of one filter workgroup (LDS).
+template <int RMAX>
+struct FilterShared {
+    float G[(2 * RMAX + 15) * table_stride(RMAX)];
+    Rec recs[kWaves][64];
+    float nq2h[kWaves][64];
+};
 
+// Filter one 16x16 output tile (tx, ty) of an image with one 256-thread
+// workgroup: builds the spatial table, then each wave filters its 8x8 block.
+// Every thread returns normally, so callers may loop over tiles with a
+// barrier between them.
+template <int RMAX, int PREC>
+__device__ void filter_tile(const float *__restrict__ D,
+                            const uint8_t *__restrict__ B,
+                            const uint8_t *__restrict__ rgb, int H, int W,
+                            const FilterParams &fp, const ListArgs &la, int tx,
+                            int ty, float *__restrict__ out,
+                            uint8_t *__restrict__ mask, float2 *__restrict__ aux,
+                            FilterShared<RMAX> &sh) {
     const int r = fp.radius;
     const int ts = table_stride(r);
-    const int tile = xcd_tile(blockIdx.x, n_pad);
-    if (tile >= n_tiles) return;  // whole workgroup leaves together
-
     // spatial table: clamped exponents (FP32) or weights (FP16 range)
-    build_table(G, r, ts, fp.ks, PREC != JBFD_FP32);
+    build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
     __syncthreads();
 
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int lane = threadIdx.x & 63;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int bx = tx * kTile + (wid & 1) * 8;
     const int by = ty * kTile + (wid >> 1) * 8;
     const int i = lane & 7, j = lane >> 3;
@@ -250,8 +255,8 @@ __global__ __launch_bounds__(256) void k_jbf_fwd(
     const uint32_t gstride = 4u | ((uint32_t)(4 * ts) << 16);
     const float kr2 = 2.0f * fp.kr;
     const BlockWalker bw{D, B, rgb, H, W, r, la, bx, by, lane, prg, pb0, lxy,
-                         gstride, reinterpret_cast<const unsigned char *>(G),
-                         recs[wid], nq2h[wid], -fp.ks};
+                         gstride, reinterpret_cast<const unsigned char *>(sh.G),
+                         sh.recs[wid], sh.nq2h[wid], -fp.ks};
 
     // Pass 1: fixed per-lane shift. Every exponent E = -kr c - ks s is <= 0,
     // so a = fma(2kr, t, -kr|p|^2) + G (the fma rounds once, relative to the
@@ -334,6 +339,19 @@ __global__ __launch_bounds__(256) void k_jbf_fwd(
     }
 }
 
+template <int RMAX, int PREC>
+__global__ __launch_bounds__(256) void k_jbf_fwd(
+    const float *__restrict__ D, const uint8_t *__restrict__ B,
+    const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
+    int tiles_x, int n_tiles, int n_pad, ListArgs la, float *__restrict__ out,
+    uint8_t *__restrict__ mask, float2 *__restrict__ aux) {
+    __shared__ FilterShared<RMAX> sh;
+    const int tile = xcd_tile(blockIdx.x, n_pad);
+    if (tile >= n_tiles) return;  // whole workgroup leaves together
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    filter_tile<RMAX, PREC>(D, B, rgb, H, W, fp, la, tx, ty, out, mask, aux, sh);
+}
+
 hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
                                   const uint8_t *rgb, int32_t H, int32_t W,
                                   int32_t radius, void *ws, size_t ws_bytes,
@@ -386,6 +404,55 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
         else
             k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<n_pad, 256, 0, s>>>(
                 D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, la, out, mask, nullptr);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace jbfd
+
+namespace jbfd {
+
+// Filter tiles of every view of a batch: a fixed grid walks the flattened
+// tile space (views back to back); each workgroup finds its view by a
+// binary search of the table's tile offsets (wave-uniform scalar loads).
+template <int RMAX, int PREC>
+__global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restrict__ hdr,
+                                                      const BatchView *__restrict__ views) {
+    __shared__ FilterShared<RMAX> sh;
+    const int n_views = hdr->n_views;
+    const int total = hdr->total_tiles;
+    const ListArgs none{nullptr, nullptr, nullptr, 0, 0};
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = n_views - 1;
+        while (lo < hi) {                  // last view with tile_off <= t
+            const int mid = (lo + hi + 1) >> 1;
+            if (views[mid].tile_off <= t) lo = mid; else hi = mid - 1;
+        }
+        const BatchView &v = views[lo];
+        const int local = t - v.tile_off;
+        const int ty = local / v.tiles_x, tx = local - ty * v.tiles_x;
+        const FilterParams fp{v.radius, v.kr, v.ks};
+        filter_tile<RMAX, PREC>(v.sd, v.sv, v.rgb, v.H, v.W, fp, none, tx, ty,
+                                v.out, v.mask, nullptr, sh);
+        __syncthreads();   // the next tile rebuilds the table
+    }
+}
+
+hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
+                               int32_t max_radius, jbfd_precision prec,
+                               hipStream_t s) {
+    const int grid = 2048;   // 8 workgroups per CU
+    if (max_radius <= 16) {
+        if (prec == JBFD_FP32)
+            k_batch_filter<16, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views);
+        else
+            k_batch_filter<16, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr, views);
+    } else {
+        if (prec == JBFD_FP32)
+            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views);
+        else
+            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr,
+                                                                                views);
     }
     return hipGetLastError();
 }

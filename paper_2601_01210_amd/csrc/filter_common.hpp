@@ -10,7 +10,7 @@ namespace jbfd {
 
 
 constexpr int kWaves = 4;          // waves per workgroup (2x2 blocks of 8x8)
-constexpr int kTile = 16;          // workgroup tile edge in pixels
+constexpr int kTile = kTileEdge;   // workgroup tile edge in pixels
 constexpr float kRescaleAbove = 12.0f;
 constexpr float kShiftInit = 8388608.0f;  // 2^23
 constexpr float kClampExp = -60.0f;       // pass-1 floor of each exponent part

@@ -19,6 +19,7 @@ struct Intr {
 };
 
 constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int kTileEdge = 16;   // filter workgroup tile edge in pixels
 
 // Filter parameters in log2 units: weight = exp2(-kr*c - ks*s), with
 // kr = log2(e) / (2 sigma_r^2) and ks = log2(e) / (2 sigma_s^2).
@@ -55,5 +56,37 @@ hipError_t launch_densify_backward(const float *D, const uint8_t *B,
                                    void *ws, hipStream_t s);
 
 size_t backward_ws_bytes(int32_t H, int32_t W);
+
+// Device-side descriptor table of a batch (written by jbfd_batch_prepare).
+struct BatchView {
+    const float *pts;
+    int64_t n_pts;
+    double pose[12];
+    double fx, fy, cx, cy;
+    int32_t W, H;
+    const uint8_t *rgb;
+    uint64_t *zbuf;
+    float *sd;
+    uint8_t *sv;
+    float *out;
+    uint8_t *mask;
+    int32_t radius;
+    float kr, ks;
+    int32_t tiles_x;
+    int32_t tile_off;   // exclusive prefix of filter tiles over the views
+    int32_t n_tiles;
+};
+
+struct BatchHeader {
+    int32_t n_views;
+    int32_t total_tiles;
+    int64_t pad;
+};
+
+hipError_t launch_batch(const void *d_table, int32_t max_radius,
+                        jbfd_precision prec, hipStream_t s);
+hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
+                               int32_t max_radius, jbfd_precision prec,
+                               hipStream_t s);
 
 }  // namespace jbfd

@@ -36,80 +36,147 @@ __global__ __launch_bounds__(256) void k_fill_keys(uint64_t *__restrict__ keys,
     }
 }
 
+// Project point i; false if it is culled. Otherwise key and pixel index.
+__device__ inline bool project_one(const float *__restrict__ pts, int64_t i,
+                                   const double *__restrict__ m, double fx,
+                                   double fy, double cx, double cy, int32_t w,
+                                   int32_t h, unsigned long long &key,
+                                   int64_t &pix) {
+    const double x = (double)pts[3 * i + 0];
+    const double y = (double)pts[3 * i + 1];
+    const double z = (double)pts[3 * i + 2];
+    // each row summed left to right; no contraction into FMA
+    double X = m[0] * x;
+    X = X + m[1] * y;
+    X = X + m[2] * z;
+    X = X + m[3];
+    double Y = m[4] * x;
+    Y = Y + m[5] * y;
+    Y = Y + m[6] * z;
+    Y = Y + m[7];
+    double Z = m[8] * x;
+    Z = Z + m[9] * y;
+    Z = Z + m[10] * z;
+    Z = Z + m[11];
+    if (!(Z > 0.0) || !__builtin_isfinite(Z)) return false;
+    const double u = fx * (X / Z) + cx;
+    const double v = fy * (Y / Z) + cy;
+    if (!(u >= 0.0 && u < (double)w)) return false;
+    if (!(v >= 0.0 && v < (double)h)) return false;
+    const int64_t col = (int64_t)__builtin_floor(u);
+    const int64_t row = (int64_t)__builtin_floor(v);
+    const float zf = (float)Z;
+    if (zf == 0.0f || __builtin_isinf(zf)) return false;
+    key = ((unsigned long long)__float_as_uint(zf) << 32) |
+          (unsigned long long)(uint32_t)i;
+    pix = row * w + col;
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ pts,
                                                  int64_t n, Pose P, Intr K,
                                                  unsigned long long *__restrict__ keys) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += stride) {
-        const double x = (double)pts[3 * i + 0];
-        const double y = (double)pts[3 * i + 1];
-        const double z = (double)pts[3 * i + 2];
-        // each row summed left to right; no contraction into FMA
-        double X = P.m[0] * x;
-        X = X + P.m[1] * y;
-        X = X + P.m[2] * z;
-        X = X + P.m[3];
-        double Y = P.m[4] * x;
-        Y = Y + P.m[5] * y;
-        Y = Y + P.m[6] * z;
-        Y = Y + P.m[7];
-        double Z = P.m[8] * x;
-        Z = Z + P.m[9] * y;
-        Z = Z + P.m[10] * z;
-        Z = Z + P.m[11];
-        if (!(Z > 0.0) || !__builtin_isfinite(Z)) continue;
-        const double u = K.fx * (X / Z) + K.cx;
-        const double v = K.fy * (Y / Z) + K.cy;
-        if (!(u >= 0.0 && u < (double)K.w)) continue;
-        if (!(v >= 0.0 && v < (double)K.h)) continue;
-        const int64_t col = (int64_t)__builtin_floor(u);
-        const int64_t row = (int64_t)__builtin_floor(v);
-        const float zf = (float)Z;
-        if (zf == 0.0f || __builtin_isinf(zf)) continue;
-        const unsigned long long key =
-            ((unsigned long long)__float_as_uint(zf) << 32) |
-            (unsigned long long)(uint32_t)i;
-        atomicMin(keys + row * K.w + col, key);
+        unsigned long long key;
+        int64_t pix;
+        if (project_one(pts, i, P.m, K.fx, K.fy, K.cx, K.cy, K.w, K.h, key, pix))
+            atomicMin(keys + pix, key);
     }
 }
 
-// Four pixels per thread: two 16-byte key loads, one 16-byte depth store and
-// one 4-byte mask store; the last group may be partial.
+// Decode pixels [p0, min(p0+4, npix)): two 16-byte key loads, one 16-byte
+// depth store and one 4-byte mask store when aligned, else per pixel.
+__device__ inline void decode4(const uint64_t *__restrict__ keys, int64_t npix,
+                               int64_t p0, bool vec, float *__restrict__ depth,
+                               uint8_t *__restrict__ valid) {
+    if (vec && p0 + 4 <= npix) {
+        const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(keys + p0);
+        const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(keys + p0 + 2);
+        const uint64_t k[4] = {a.x, a.y, b.x, b.y};
+        float d[4];
+        uint32_t m = 0;
+        for (int t = 0; t < 4; ++t) {
+            const bool hit = k[t] != kEmptyKey;
+            d[t] = hit ? __uint_as_float((uint32_t)(k[t] >> 32)) : 0.0f;
+            m |= (uint32_t)hit << (8 * t);
+        }
+        if (depth)
+            *reinterpret_cast<float4 *>(depth + p0) = make_float4(d[0], d[1], d[2], d[3]);
+        if (valid) *reinterpret_cast<uint32_t *>(valid + p0) = m;
+    } else {
+        for (int64_t p = p0; p < npix && p < p0 + 4; ++p) {
+            const uint64_t k = keys[p];
+            const bool hit = k != kEmptyKey;
+            if (depth) depth[p] = hit ? __uint_as_float((uint32_t)(k >> 32)) : 0.0f;
+            if (valid) valid[p] = (uint8_t)hit;
+        }
+    }
+}
+
+__device__ inline bool decode_vec_ok(const uint64_t *keys, const float *depth,
+                                     const uint8_t *valid) {
+    return ((reinterpret_cast<uintptr_t>(depth) & 15) == 0) &&
+           ((reinterpret_cast<uintptr_t>(valid) & 3) == 0) &&
+           ((reinterpret_cast<uintptr_t>(keys) & 15) == 0);
+}
+
 __global__ __launch_bounds__(256) void k_decode(const uint64_t *__restrict__ keys,
                                                 int64_t npix,
                                                 float *__restrict__ depth,
                                                 uint8_t *__restrict__ valid) {
     const int64_t groups = (npix + 3) / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const bool vec = ((reinterpret_cast<uintptr_t>(depth) & 15) == 0) &&
-                     ((reinterpret_cast<uintptr_t>(valid) & 3) == 0) &&
-                     ((reinterpret_cast<uintptr_t>(keys) & 15) == 0);
+    const bool vec = decode_vec_ok(keys, depth, valid);
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
-         g += stride) {
-        const int64_t p0 = g * 4;
-        if (vec && p0 + 4 <= npix) {
-            const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(keys + p0);
-            const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(keys + p0 + 2);
-            const uint64_t k[4] = {a.x, a.y, b.x, b.y};
-            float d[4];
-            uint32_t m = 0;
-            for (int t = 0; t < 4; ++t) {
-                const bool hit = k[t] != kEmptyKey;
-                d[t] = hit ? __uint_as_float((uint32_t)(k[t] >> 32)) : 0.0f;
-                m |= (uint32_t)hit << (8 * t);
-            }
-            if (depth)
-                *reinterpret_cast<float4 *>(depth + p0) = make_float4(d[0], d[1], d[2], d[3]);
-            if (valid) *reinterpret_cast<uint32_t *>(valid + p0) = m;
-        } else {
-            for (int64_t p = p0; p < npix && p < p0 + 4; ++p) {
-                const uint64_t k = keys[p];
-                const bool hit = k != kEmptyKey;
-                if (depth) depth[p] = hit ? __uint_as_float((uint32_t)(k >> 32)) : 0.0f;
-                if (valid) valid[p] = (uint8_t)hit;
-            }
+         g += stride)
+        decode4(keys, npix, g * 4, vec, depth, valid);
+}
+
+// ---------------------------------------------------------------------------
+// batches: fixed grids that loop over the views of a descriptor table and
+// grid-stride over each view's pixels or points
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_batch_clear(const BatchHeader *__restrict__ hdr,
+                                                     const BatchView *__restrict__ views) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int v = 0; v < hdr->n_views; ++v) {
+        uint64_t *keys = views[v].zbuf;
+        const int64_t n = (int64_t)views[v].W * views[v].H;
+        for (int64_t i = tid; i < n; i += stride) keys[i] = kEmptyKey;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_project(const BatchHeader *__restrict__ hdr,
+                                                       const BatchView *__restrict__ views) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int v = 0; v < hdr->n_views; ++v) {
+        const BatchView &bv = views[v];
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(bv.zbuf);
+        for (int64_t i = tid; i < bv.n_pts; i += stride) {
+            unsigned long long key;
+            int64_t pix;
+            if (project_one(bv.pts, i, bv.pose, bv.fx, bv.fy, bv.cx, bv.cy, bv.W,
+                            bv.H, key, pix))
+                atomicMin(keys + pix, key);
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_decode(const BatchHeader *__restrict__ hdr,
+                                                      const BatchView *__restrict__ views) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int v = 0; v < hdr->n_views; ++v) {
+        const BatchView &bv = views[v];
+        const int64_t npix = (int64_t)bv.W * bv.H;
+        const bool vec = decode_vec_ok(bv.zbuf, bv.sd, bv.sv);
+        for (int64_t g = tid; g < (npix + 3) / 4; g += stride)
+            decode4(bv.zbuf, npix, g * 4, vec, bv.sd, bv.sv);
     }
 }
 
@@ -131,6 +198,20 @@ hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
     if (depth || valid)
         k_decode<<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
     return hipGetLastError();
+}
+
+hipError_t launch_batch(const void *d_table, int32_t max_radius,
+                        jbfd_precision prec, hipStream_t s) {
+    const BatchHeader *hdr = static_cast<const BatchHeader *>(d_table);
+    const BatchView *views = reinterpret_cast<const BatchView *>(
+        static_cast<const unsigned char *>(d_table) + sizeof(BatchHeader));
+    const int grid = 1024;   // four workgroups per CU, grid-striding
+    k_batch_clear<<<grid, 256, 0, s>>>(hdr, views);
+    k_batch_project<<<grid, 256, 0, s>>>(hdr, views);
+    k_batch_decode<<<grid, 256, 0, s>>>(hdr, views);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_batch_filter(hdr, views, max_radius, prec, s);
 }
 
 }  // namespace jbfd

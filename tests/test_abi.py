@@ -135,3 +135,81 @@ def test_backward_workspace_checks(L):
                                  C.c_float(10), f, None, f, f, f, f, need,
                                  None)
     assert st == JBFD_EINVAL
+
+
+def _views(n, w=40, h=30, radius=5, n_points=100):
+    from paper_2601_01210_amd.binding import Intrinsics, View
+    out = []
+    for k in range(n):
+        v = View()
+        base = 0x10000 * (k + 1)
+        v.points, v.n_points = base + 0x100, n_points
+        v.cam_from_world = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+        v.K = Intrinsics(20.0, 20.0, w / 2, h / 2, w + k, h + 2 * k)
+        v.rgb, v.radius, v.sigma_s, v.sigma_r = base + 0x200, radius, 3.0, 12.0
+        v.zbuf, v.sparse_depth, v.sparse_valid = base + 0x300, base + 0x400, \
+            base + 0x500
+        v.dense_depth, v.dense_valid = base + 0x600, base + 0x700
+        out.append(v)
+    return out
+
+
+def test_batch_prepare_serialises_table(L):
+    """The table is a 16-byte header {n_views, total_tiles, pad} then one
+    entry per view; tiles are 16x16 and numbered view after view."""
+    import numpy as np
+    from paper_2601_01210_amd import binding
+    views = _views(3)
+    n = binding.batch_table_bytes(3)
+    assert n > 16 and binding.batch_table_bytes(0) == 0
+    host = np.zeros(n, np.uint8)
+    binding.batch_prepare_raw(views, host)
+    hdr = host[:8].view(np.int32)
+    tiles = [((40 + k + 15) // 16) * ((30 + 2 * k + 15) // 16) for k in range(3)]
+    assert hdr[0] == 3 and hdr[1] == sum(tiles)
+    # table too small
+    with pytest.raises(binding.JbfdError) as e:
+        binding.batch_prepare_raw(views, np.zeros(n - 8, np.uint8))
+    assert e.value.status == binding.JBFD_ENOSPC
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("rgb", 0, b"null"), ("dense_valid", 0, b"null"), ("n_points", -1, b"n_points"),
+    ("radius", 40, b"radius"), ("sigma_s", 0.0, b"sigma"),
+    ("sigma_r", float("nan"), b"sigma")])
+def test_batch_prepare_rejects_bad_views(L, field, value, msg):
+    import numpy as np
+    from paper_2601_01210_amd import binding
+    views = _views(2)
+    setattr(views[1], field, value)
+    host = np.zeros(binding.batch_table_bytes(2), np.uint8)
+    with pytest.raises(binding.JbfdError) as e:
+        binding.batch_prepare_raw(views, host)
+    assert e.value.status == binding.JBFD_EINVAL
+    assert b"view 1" in L.jbfd_last_error() and msg in L.jbfd_last_error()
+
+
+def test_batch_prepare_rejects_bad_pose_and_size(L):
+    import numpy as np
+    from paper_2601_01210_amd import binding
+    host = np.zeros(binding.batch_table_bytes(1), np.uint8)
+    v = _views(1)
+    v[0].cam_from_world[7] = float("inf")
+    with pytest.raises(binding.JbfdError):
+        binding.batch_prepare_raw(v, host)
+    v = _views(1, w=40000)
+    with pytest.raises(binding.JbfdError):
+        binding.batch_prepare_raw(v, host)
+    v = _views(1, n_points=0)
+    v[0].points = 0                      # no points: a null pointer is fine
+    binding.batch_prepare_raw(v, host)
+
+
+def test_batch_run_rejects_bad_arguments(L):
+    from paper_2601_01210_amd.binding import JBFD_EINVAL
+    fake = C.c_void_p(0x1000)
+    assert L.jbfd_batch_run(None, 5, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(C.c_void_p(0x1004), 5, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, 33, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, -1, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, 5, 7, None) == JBFD_EINVAL
