@@ -429,3 +429,67 @@ def holdout_split(rng: np.random.Generator, n: int, fraction: float = 0.1):
     m = np.zeros(n, dtype=bool)
     m[idx] = True
     return m
+
+
+# --------------------------------------------------------------------------
+# serving workload: many viewpoints, each with its own world frame, and
+# frames arriving on jittered 30 fps clocks
+# --------------------------------------------------------------------------
+
+SERVING_SIZES = ((1280, 720), (1920, 1080), (3840, 2160))
+
+
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    """Uniformly random rotation matrix (QR of a Gaussian matrix)."""
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def with_random_pose(frame: Frame, rng: np.random.Generator,
+                     max_offset: float = 10.0) -> Frame:
+    """The same frame expressed in a random world frame: the camera gets the
+    pose [R|t] (camera from world) and the points become R^T (p - t),
+    rounded to float32."""
+    R = random_rotation(rng)
+    t = rng.uniform(-max_offset, max_offset, size=3)
+    pw = (frame.points.astype(np.float64) - t) @ R      # rows: R^T (p - t)
+    cam = dataclasses.replace(frame.camera, pose=np.hstack([R, t[:, None]]))
+    return dataclasses.replace(frame, points=pw.astype(np.float32),
+                               camera=cam)
+
+
+def serving_specs(rng: np.random.Generator, n_views: int = 16,
+                  sizes=SERVING_SIZES, n_range=(50000, 400000)):
+    """Per viewpoint (width, height, n_points, seed): resolution drawn from
+    ``sizes``, point count log-uniform in ``n_range``."""
+    specs = []
+    for _ in range(n_views):
+        w, h = sizes[int(rng.integers(0, len(sizes)))]
+        n = log_uniform_int(rng, *n_range)
+        specs.append((int(w), int(h), int(n), int(rng.integers(0, 2 ** 63))))
+    return specs
+
+
+def serving_view(spec) -> Frame:
+    """One serving viewpoint from its spec: a small-view scene (6 boxes,
+    scan widened to reach the point count) in its own random world frame."""
+    w, h, n, seed = spec
+    rng = np.random.default_rng(seed)
+    return with_random_pose(small_view(rng, w, h, n_points=n), rng)
+
+
+def arrival_times(rng: np.random.Generator, n_views: int, duration_s: float,
+                  rate_hz: float = 30.0):
+    """Sorted (time, viewpoint) pairs: each viewpoint starts at a random
+    phase and then emits frames with exponential gaps of mean 1/rate_hz."""
+    out = []
+    for v in range(n_views):
+        t = rng.uniform(0.0, 1.0 / rate_hz)
+        while t < duration_s:
+            out.append((float(t), v))
+            t += rng.exponential(1.0 / rate_hz)
+    out.sort()
+    return out

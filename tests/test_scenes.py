@@ -1,5 +1,6 @@
 """The seeded generator: determinism and workload shapes."""
 import numpy as np
+import pytest
 
 from synth import scenes as S
 
@@ -38,3 +39,28 @@ def test_log_uniform_range():
     rng = np.random.default_rng(0)
     v = [S.log_uniform_int(rng, 20000, 250000) for _ in range(200)]
     assert min(v) >= 20000 and max(v) <= 250000
+
+
+def test_random_pose_is_rigid_and_invertible():
+    rng = np.random.default_rng(4)
+    f = S.small_view(rng, 64, 48, n_points=500)
+    g = S.with_random_pose(f, rng)
+    R, t = g.camera.pose[:, :3], g.camera.pose[:, 3]
+    np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-12)
+    assert np.linalg.det(R) == pytest.approx(1.0)
+    back = g.points.astype(np.float64) @ R.T + t          # camera frame again
+    np.testing.assert_allclose(back, f.points, atol=1e-4)
+
+
+def test_serving_specs_and_arrivals():
+    rng = np.random.default_rng(5)
+    specs = S.serving_specs(rng, 64)
+    assert all((w, h) in S.SERVING_SIZES for w, h, _, _ in specs)
+    assert all(50000 <= n <= 400000 for _, _, n, _ in specs)
+    arr = S.arrival_times(np.random.default_rng(6), 16, 20.0)
+    ts = np.array([t for t, _ in arr])
+    assert np.all(np.diff(ts) >= 0) and ts.max() < 20.0
+    # 16 viewpoints at 30 Hz for 20 s: about 9600 frames (Poisson)
+    assert abs(len(arr) - 9600) < 5 * np.sqrt(9600)
+    per = np.bincount([v for _, v in arr], minlength=16)
+    assert per.min() > 500
