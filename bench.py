@@ -1,19 +1,29 @@
 """Benchmark: Full-HD LiDAR densification frames/s on one MI355X.
 
-One step = the whole hot path on one synthetic Full-HD viewpoint whose
-inputs are already resident in HBM: projection of the ~2e5 merged points of
-three staggered 32-beam sweeps (clear + project + decode), the per-strip
-sample lists, and the r = 15, sigma_s = 6, sigma_r = 15 joint bilateral
-filter. Input and output
-buffers rotate over enough distinct copies (> 512 MB) that the 256 MB
-Infinity Cache cannot hold them.
+Main line (``value``): one step = the whole hot path on one synthetic
+Full-HD viewpoint whose inputs are already resident in HBM: projection of
+the ~2e5 merged points of three staggered 32-beam sweeps (clear + project +
+decode), the per-strip sample lists, and the r = 15, sigma_s = 6,
+sigma_r = 15 joint bilateral filter. Input and output buffers rotate over
+enough distinct copies (> 512 MB) that the 256 MB Infinity Cache cannot
+hold them. Printed beside it: per-kernel durations from HIP events on the
+launch stream, the filter kernel's roofline position, a device copy
+ceiling, the plain per-frame end-to-end path, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
 
-Printed (one JSON line): frames/s, ms per step, per-kernel durations from
-HIP events recorded on the launch stream, the filter kernel's roofline
-position (algorithmic FLOPs / measured duration vs the FP32 vector peak),
-the plain per-frame end-to-end path (pinned-host upload, project, filter,
-download, synchronise) with p50/p99 latency, and the FP64 CPU oracle timed
-on a bounded sample of the same workload on the host cores.
+Further legs (``--legs``, all on by default):
+
+* ``batched``  eight uneven views (720p/1080p, 20k-250k points, r = 5) in
+  one graph-replayed batch vs the same views as single-view calls, FP32 and
+  FP16 range weights;
+* ``fp16``     the Full-HD filter with FP16 range weights vs FP32;
+* ``serving``  sixteen viewpoints (720p/1080p/4K, 50k-400k points, r = 5,
+  FP16 range weights) with frames arriving on jittered 30 fps clocks:
+  served (continuous batching) vs plain (one frame at a time), frames/s,
+  Full-HD-equivalent frames/s and p50/p99 latency from arrival to results
+  in pinned host memory; then a saturation sweep of the arrival rate;
+* ``fit``      200 Adam steps of the self-supervised sigma fit on four
+  Full-HD frames with 10% of the points held out.
 """
 from __future__ import annotations
 
@@ -21,6 +31,7 @@ import argparse
 import hashlib
 import json
 import math
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -31,10 +42,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from synth import scenes as S  # noqa: E402  (numpy only)
+
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 FLOPS_PER_PAIR = 14                 # per (output pixel, valid sample) pair
 ROTATE_BYTES = 600 << 20            # > 512 MB of distinct buffers
+FHD = 1920 * 1080
+LATENCY_TARGET_MS = 33.0
+LEGS = ("batched", "fp16", "serving", "fit")
 
 
 def parse():
@@ -51,7 +67,26 @@ def parse():
     ap.add_argument("--copy-mb", type=int, default=512,
                     help="size of the plain device copy that calibrates the "
                          "HBM byte counters and gives the copy ceiling")
-    return ap.parse_args()
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated extra legs: " + ",".join(LEGS) +
+                         " (empty for none)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured arrival window of each serving run")
+    ap.add_argument("--serve-warmup", type=float, default=2.0,
+                    help="arrivals in this first window are not counted")
+    ap.add_argument("--sat-seconds", type=float, default=2.5,
+                    help="arrival window of each saturation-sweep run")
+    ap.add_argument("--sat-max-frames", type=int, default=4000)
+    ap.add_argument("--budget-gb", type=float, default=16.0,
+                    help="HBM budget of the served path's slots")
+    ap.add_argument("--fit-steps", type=int, default=200)
+    ap.add_argument("--gen-workers", type=int, default=16)
+    args = ap.parse_args()
+    args.legs = [x for x in args.legs.split(",") if x]
+    for x in args.legs:
+        if x not in LEGS:
+            ap.error(f"unknown leg {x}")
+    return args
 
 
 def window_pairs(valid: np.ndarray, r: int) -> int:
@@ -87,6 +122,278 @@ def committed_traffic(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _fit_view(seed):
+    """A config-1-generator scene at Full-HD (6 boxes, one 16-beam sweep)."""
+    return S.small_view(np.random.default_rng(seed), 1920, 1080)
+
+
+def _gen(job):
+    kind, arg = job
+    return S.serving_view(arg) if kind == "serve" else _fit_view(arg)
+
+
+def generate(args):
+    """Every workload, on the CPU, before the GPU is touched (the pool
+    forks; no process here has initialised HIP yet)."""
+    t = time.time()
+    out = {"fullhd": S.fullhd_view(S.seeded(2, args.seed))}
+    if "batched" in args.legs:
+        out["batch"] = S.batch_views(S.seeded(3))
+    jobs = []
+    if "serving" in args.legs:
+        out["serve_specs"] = S.serving_specs(S.seeded(4))
+        jobs += [("serve", s) for s in out["serve_specs"]]
+    if "fit" in args.legs:
+        seeds = [int(x) for x in S.seeded(5).integers(0, 2 ** 63, size=4)]
+        jobs += [("fit", s) for s in seeds]
+    if jobs:
+        n = max(1, min(args.gen_workers, len(jobs)))
+        with mp.get_context("fork").Pool(n) as pool:
+            res = pool.map(_gen, jobs, chunksize=1)
+        out["serve"] = [f for (k, _), f in zip(jobs, res) if k == "serve"]
+        out["fit"] = [f for (k, _), f in zip(jobs, res) if k == "fit"]
+    out["seconds"] = round(time.time() - t, 2)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# legs
+# ---------------------------------------------------------------------------
+
+def batched_leg(torch, dev, frames, steps):
+    from paper_2601_01210_amd import (BatchView, Precision, batch_run,
+                                      batch_upload, densify, densify_prepare,
+                                      densify_workspace, project)
+    max_r = max(f.radius for f in frames)
+    sets = []
+    for _ in range(3):                      # three copies: > 512 MB together
+        views = []
+        for f in frames:
+            c = f.camera
+            views.append(BatchView(torch.from_numpy(f.points).to(dev), c.pose,
+                                   c.intrinsics()[:4], c.width, c.height,
+                                   torch.from_numpy(f.rgb).to(dev), f.radius,
+                                   f.sigma_s, f.sigma_r).allocate())
+        table, _ = batch_upload(views)
+        ws = [densify_workspace(v.height, v.width, v.radius,
+                                v.points.shape[0], dev) for v in views]
+        sets.append((views, table, ws))
+    torch.cuda.synchronize()
+    px = sum(f.camera.width * f.camera.height for f in frames)
+    npts = sum(len(f.points) for f in frames)
+    min_bytes = 12 * npts + 8 * px          # points, RGB, depth + mask out
+    res = {"views": len(frames), "pixels": px, "points": npts,
+           "fhd_equivalent": round(px / FHD, 3),
+           "sizes": [f"{f.camera.width}x{f.camera.height}" for f in frames],
+           "radius": max_r, "algorithmic_bytes": min_bytes}
+    stream = torch.cuda.current_stream(dev)
+    for prec in (Precision.FP32, Precision.FP16_RANGE):
+        graphs = []
+        for views, table, _ in sets:
+            batch_run(table, max_r, prec)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, capture_error_mode="thread_local"):
+                batch_run(table, max_r, prec)
+            graphs.append(g)
+        torch.cuda.synchronize()
+
+        def per_view(k):
+            views, _, ws = sets[k % len(sets)]
+            for v, w in zip(views, ws):
+                project(v.points, v.pose, v.intrinsics, v.width, v.height,
+                        v.zbuf, v.sparse_depth, v.sparse_valid)
+                densify_prepare(v.sparse_depth, v.sparse_valid, v.rgb,
+                                v.radius, w)
+                densify(v.sparse_depth, v.sparse_valid, v.rgb, v.radius,
+                        v.sigma_s, v.sigma_r, prec, v.dense_depth,
+                        v.dense_valid, ws=w, lists_ready=True)
+
+        timings = {}
+        for name, fn in (("batched_graph",
+                          lambda k: graphs[k % len(graphs)].replay()),
+                         ("per_view_calls", per_view)):
+            for k in range(5):
+                fn(k)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for k in range(steps):
+                fn(k)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            timings[name] = ev[0].elapsed_time(ev[1]) / steps
+        b, p = timings["batched_graph"], timings["per_view_calls"]
+        res[prec.name.lower()] = {
+            "batched_ms": round(b, 4), "per_view_calls_ms": round(p, 4),
+            "batched_fhd_frames_per_s": round(px / FHD / (b * 1e-3), 1),
+            "per_view_fhd_frames_per_s": round(px / FHD / (p * 1e-3), 1),
+            "batched_hbm_frac_algorithmic": round(
+                min_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del graphs
+    del sets
+    torch.cuda.synchronize()
+    return res
+
+
+def fp16_leg(torch, dev, b, r, ss, sr, steps):
+    from paper_2601_01210_amd import Precision, densify
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for prec in (Precision.FP32, Precision.FP16_RANGE):
+        for _ in range(5):
+            densify(b["d"], b["v"], b["rgb"], r, ss, sr, prec, out=b["out"],
+                    mask=b["m"], ws=b["ws"], lists_ready=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            densify(b["d"], b["v"], b["rgb"], r, ss, sr, prec, out=b["out"],
+                    mask=b["m"], ws=b["ws"], lists_ready=True)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        out[prec.name.lower() + "_filter_ms"] = round(
+            ev[0].elapsed_time(ev[1]) / steps, 4)
+    out["fp16_over_fp32"] = round(out["fp16_range_filter_ms"] /
+                                  out["fp32_filter_ms"], 3)
+    return out
+
+
+def serving_leg(torch, dev, frames, args):
+    from paper_2601_01210_amd import Precision
+    from paper_2601_01210_amd import serve as SV
+    prec = Precision.FP16_RANGE
+    vps, inputs = [], []
+    for vid, f in enumerate(frames):
+        c = f.camera
+        vps.append(SV.Viewpoint(vid, c.width, c.height, c.intrinsics()[:4],
+                                c.pose, f.radius, f.sigma_s, f.sigma_r,
+                                len(f.points)))
+        inputs.append((torch.from_numpy(f.points).pin_memory(),
+                       torch.from_numpy(f.rgb).pin_memory()))
+
+    def requests(rate_mult, duration, seed):
+        arr = S.arrival_times(np.random.default_rng(seed), len(vps), duration,
+                              30.0 * rate_mult)
+        return [SV.Request(vps[v], i, t, inputs[v][0], inputs[v][1],
+                           inputs[v][0].shape[0]) for i, (t, v) in enumerate(arr)]
+
+    max_batch = 16
+    ex = SV.GpuExecutor(dev, prec, max_batch=max_batch, max_inflight=2,
+                        timing=True)
+    ex.prewarm(max(v.radius for v in vps))
+    srv = SV.Server(ex, int(args.budget_gb * (1 << 30)), max_batch=max_batch,
+                    max_inflight=2)
+    srv.prefill([v.key for v in vps], 2)
+    plain = SV.PlainRunner(prec, dev)
+
+    def served_run(reqs, warm):
+        srv.batch_sizes, ex.kernel_ms = [], []
+        t = time.perf_counter()
+        srv.run(reqs)
+        wall = time.perf_counter() - t
+        st = SV.summarize(reqs, warm, srv.batch_sizes).as_dict()
+        st["kernel_ms_per_batch"] = round(float(np.mean(ex.kernel_ms)), 4)
+        st["device_busy_frac"] = round(sum(ex.kernel_ms) * 1e-3 / wall, 4)
+        return st
+
+    def plain_run(reqs, warm):
+        plain.run(reqs)
+        return SV.summarize(reqs, warm).as_dict()
+
+    def rounded(st):
+        return {k: (round(v, 3) if isinstance(v, float) else v)
+                for k, v in st.items()}
+
+    dur = args.serve_seconds + args.serve_warmup
+    res = {"viewpoints": len(vps),
+           "sizes": [f"{v.width}x{v.height}" for v in vps],
+           "points": [v.max_points for v in vps],
+           "mean_fhd_equivalent_per_frame": round(
+               float(np.mean([v.width * v.height for v in vps])) / FHD, 3),
+           "precision": "fp16_range", "radius": vps[0].radius,
+           "offered_frames_per_s": 30.0 * len(vps),
+           "arrival_seconds": args.serve_seconds,
+           "warmup_seconds": args.serve_warmup,
+           "budget_bytes": srv.pool.budget}
+    res["served"] = rounded(served_run(requests(1, dur, 40), args.serve_warmup))
+    res["plain"] = rounded(plain_run(requests(1, dur, 40), args.serve_warmup))
+    res["slot_bytes_peak"] = srv.pool.peak
+    res["slot_allocations"] = srv.pool.allocations
+
+    # saturation: raise the arrival rate until p99 exceeds the target or the
+    # path falls behind the offered rate
+    sweep = {"served": [], "plain": []}
+    for name, fn in (("served", served_run), ("plain", plain_run)):
+        for mult in (1.5, 2, 2.5, 3, 3.5, 4, 5, 6, 8, 10, 12, 16, 24, 32):
+            rate = 30.0 * mult * len(vps)
+            d = min(args.sat_seconds, args.sat_max_frames / rate)
+            warm = 0.2 * d
+            st = fn(requests(mult, d, 41 + int(10 * mult)), warm)
+            ok = (st["p99_ms"] <= LATENCY_TARGET_MS and
+                  st["frames_per_s"] >= 0.9 * rate)
+            sweep[name].append({"offered_frames_per_s": rate,
+                                "frames_per_s": round(st["frames_per_s"], 1),
+                                "fhd_frames_per_s": round(st["fhd_frames_per_s"], 1),
+                                "p50_ms": round(st["p50_ms"], 3),
+                                "p99_ms": round(st["p99_ms"], 3),
+                                "ok": ok})
+            if not ok:
+                break
+    res["saturation"] = sweep
+    for name in ("served", "plain"):
+        good = [x for x in sweep[name] if x["ok"]]
+        res[f"{name}_max_fhd_frames_per_s_p99_under_33ms"] = (
+            max(x["fhd_frames_per_s"] for x in good) if good else None)
+    del srv, ex, plain
+    torch.cuda.synchronize()
+    return res
+
+
+def fit_leg(torch, dev, frames, steps):
+    from paper_2601_01210_amd import autograd as AG
+    from paper_2601_01210_amd import binding
+    rng = S.seeded(5)
+    fit_frames, gts = [], []
+    for f in frames:
+        c = f.camera
+        held = S.holdout_split(rng, len(f.points), 0.1)
+        pin = torch.from_numpy(np.ascontiguousarray(f.points[~held])).to(dev)
+        pout = torch.from_numpy(np.ascontiguousarray(f.points[held])).to(dev)
+        _, d, v = binding.project(pin, c.pose, c.intrinsics(), c.width, c.height)
+        td, tv = AG.heldout_targets(pout, c.pose, c.intrinsics(), c.width,
+                                    c.height)
+        fit_frames.append(AG.FitFrame(d, v, torch.from_numpy(f.rgb).to(dev),
+                                      td, tv))
+        gts.append(torch.from_numpy(f.gt_depth).to(dev))
+
+    def gt_mae(ss, sr):
+        tot, n = 0.0, 0
+        for fr, gt in zip(fit_frames, gts):
+            out, mask = binding.densify(fr.depth, fr.valid, fr.rgb, 5, ss, sr,
+                                        ws=None)
+            use = (mask == 1) & (gt > 0)
+            tot += float((out - gt).abs()[use].sum())
+            n += int(use.sum())
+        return tot / max(n, 1)
+
+    ss0, sr0 = 2.0, 40.0
+    mae0 = gt_mae(ss0, sr0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ss, sr, hist = AG.fit_sigmas(fit_frames, 5, ss0, sr0, steps=steps, lr=0.05)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    return {"frames": len(frames), "points": [len(f.points) for f in frames],
+            "steps": steps, "ms_per_step": round(el * 1e3 / max(steps, 1), 3),
+            "loss_first": round(hist[0]["loss"], 5),
+            "loss_last": round(hist[-1]["loss"], 5),
+            "sigma_s": round(ss, 4), "sigma_r": round(sr, 4),
+            "targets": hist[-1]["targets"],
+            "gt_mae_m_before": round(mae0, 5),
+            "gt_mae_m_after": round(gt_mae(ss, sr), 5)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,17 +403,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    work = generate(args)
+    print(f"[bench] workloads generated in {work['seconds']} s", flush=True)
+
     import torch
 
     from paper_2601_01210_amd import (densify, densify_prepare,
                                       densify_workspace, project)
-    from synth import scenes as S
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    t_gen = time.time()
-    frame = S.fullhd_view(S.seeded(2, args.seed))
-    t_gen = time.time() - t_gen
+    frame = work["fullhd"]
     cam = frame.camera
     H, W = cam.height, cam.width
     r, ss, sr = frame.radius, frame.sigma_s, frame.sigma_r
@@ -164,6 +471,7 @@ def main():
     wall = time.perf_counter() - t0
     step_ms = wall * 1e3 / args.steps
     fps = args.steps / wall
+    print(f"[bench] main: {fps:.1f} frames/s", flush=True)
 
     # per-kernel durations: a second pass with HIP events recorded on the
     # launch stream around each stage
@@ -237,6 +545,26 @@ def main():
            "note": "pinned H2D of points+RGB, project, filter, D2H of depth+"
                    "mask, synchronise; one frame at a time"}
 
+    legs = {}
+    if "fp16" in args.legs:
+        legs["fp16_fullhd"] = fp16_leg(torch, dev, sets[0], r, ss, sr,
+                                       max(args.steps // 2, 10))
+        print(f"[bench] fp16: {legs['fp16_fullhd']}", flush=True)
+    del sets
+    torch.cuda.synchronize()
+    if "batched" in args.legs:
+        legs["batched"] = batched_leg(torch, dev, work["batch"],
+                                      max(args.steps // 4, 10))
+        print(f"[bench] batched: fp32 {legs['batched']['fp32']}", flush=True)
+    if "serving" in args.legs:
+        legs["serving"] = serving_leg(torch, dev, work["serve"], args)
+        sv = legs["serving"]
+        print(f"[bench] serving: served {sv['served']} plain {sv['plain']}",
+              flush=True)
+    if "fit" in args.legs:
+        legs["fit"] = fit_leg(torch, dev, work["fit"], args.fit_steps)
+        print(f"[bench] fit: {legs['fit']}", flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -275,8 +603,9 @@ def main():
         "plain_e2e": e2e if args.e2e_frames > 0 else None,
         "device_copy": copy,
         "cpu_baseline": cpu,
-        "generator_s": round(t_gen, 2),
+        "generator_s": work["seconds"],
     }
+    line.update(legs)
     print(json.dumps(line), flush=True)
 
 

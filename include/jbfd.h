@@ -5,9 +5,9 @@
  * Point Cloud Densification for Low-Latency Spatial Data Transmission"
  * (arXiv 2601.01210):
  *
- *   1. jbfd_project  - merged LiDAR points are projected into the camera
- *                      view to form one sparse depth image (Sec. 2), with a
- *                      nearest-depth z-buffer;
+ *   1. jbfd_project  - the merged LiDAR points of a viewpoint become one
+ *                      sparse depth image in its camera (Sec. 2), the
+ *                      nearest point winning each pixel (z-buffer);
  *   2. jbfd_densify  - RGB-guided joint bilateral filter over that sparse
  *                      depth image (Eq. 1-4, organised as Algorithm 1),
  *                      giving a dense depth image and a validity mask;
@@ -16,8 +16,9 @@
  *                      widths (Sec. 4: the filter parameters are trainable
  *                      by backpropagation);
  *   4. jbfd_batch_run - projection + filter for many viewpoints of mixed
- *                      size in one persistent launch (Sec. 2 processes each
- *                      viewpoint independently).
+ *                      size in one fixed-grid launch sequence that covers
+ *                      every view (Sec. 2 processes each viewpoint
+ *                      independently).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -109,8 +110,9 @@ const char *jbfd_last_error(void);
 
 /*
  * Projection of merged LiDAR points into one camera and nearest-depth
- * z-buffer (Sec. 2: "merged and projected into the camera view to form a
- * single depth image"; the collision rule is the reading stated above).
+ * z-buffer (Sec. 2: the combined sweeps of a viewpoint become one sparse
+ * depth image in its camera; the collision rule is the reading stated
+ * above).
  *
  * For each point i (its index in the merged array, sweeps concatenated in
  * order): (X,Y,Z) = R p + t in double precision, summed left to right with
@@ -246,9 +248,10 @@ size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
  * jbfd_batch_table_bytes(n_views) bytes (pinned memory lets the copy be
  * asynchronous and captured); the caller copies it to device memory and
  * calls jbfd_batch_run() with that device pointer. jbfd_batch_run launches
- * fixed-size grids that read every size from the table, so the launches can
- * be captured once into a HIP graph and replayed for any batch whose table
- * has at most the captured max_views views and radii <= max_radius.
+ * fixed-size grids (clear, project, decode, filter) that read every size
+ * from the table, so the launches can be captured once into a HIP graph and
+ * replayed for any batch written into the same device table, as long as
+ * every radius stays <= the captured max_radius.
  *
  * Per view, the work is that of jbfd_project followed by jbfd_densify
  * (without sample lists) on the same definitions; outputs are identical to

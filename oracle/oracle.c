@@ -7,10 +7,10 @@
  *
  * What it computes, each function citing the passage it follows:
  *
- *   oracle_project       Sec. 2 (points merged and projected into the camera
- *                        view to form one depth image) with a nearest-depth
- *                        z-buffer; the collision rule is the reading stated
- *                        below.
+ *   oracle_project       Sec. 2 (the sweeps of one viewpoint, combined, are
+ *                        mapped into its camera as a single sparse depth
+ *                        image) with a nearest-depth z-buffer; the collision
+ *                        rule is the reading stated below.
  *   oracle_densify       Eq. 1-4 (joint bilateral filter, gather form) over
  *                        the square window of Algorithm 1, in double.
  *   oracle_densify_plain Eq. 1-4 evaluated literally (product of the two

@@ -224,7 +224,7 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
     jbfd::BatchHeader *hdr = static_cast<jbfd::BatchHeader *>(host_table);
     jbfd::BatchView *out = reinterpret_cast<jbfd::BatchView *>(
         static_cast<unsigned char *>(host_table) + sizeof(jbfd::BatchHeader));
-    int64_t tiles = 0;
+    int64_t tiles = 0, px_chunks = 0, pt_chunks = 0;
     for (int32_t v = 0; v < n_views; ++v) {
         const jbfd_view &x = views[v];
         if (!x.rgb || !x.zbuf || !x.sparse_depth || !x.sparse_valid ||
@@ -265,12 +265,19 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
         b.n_tiles = b.tiles_x * ((x.K.height + jbfd::kTileEdge - 1) / jbfd::kTileEdge);
         b.tile_off = (int32_t)tiles;
         tiles += b.n_tiles;
-        if (tiles >= ((int64_t)1 << 31))
-            return fail(JBFD_EINVAL, "batch: too many filter tiles");
+        b.px_chunk_off = (int32_t)px_chunks;
+        px_chunks += ((int64_t)x.K.width * x.K.height + jbfd::kBatchChunk - 1) /
+                     jbfd::kBatchChunk;
+        b.pt_chunk_off = (int32_t)pt_chunks;
+        pt_chunks += (x.n_points + jbfd::kBatchChunk - 1) / jbfd::kBatchChunk;
+        if (tiles >= ((int64_t)1 << 31) || px_chunks >= ((int64_t)1 << 31) ||
+            pt_chunks >= ((int64_t)1 << 31))
+            return fail(JBFD_EINVAL, "batch: too many tiles or chunks");
     }
     hdr->n_views = n_views;
     hdr->total_tiles = (int32_t)tiles;
-    hdr->pad = 0;
+    hdr->px_chunks = (int32_t)px_chunks;
+    hdr->pt_chunks = (int32_t)pt_chunks;
     return ok();
 }
 

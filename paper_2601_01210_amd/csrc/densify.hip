@@ -423,11 +423,7 @@ __global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restr
     const int total = hdr->total_tiles;
     const ListArgs none{nullptr, nullptr, nullptr, 0, 0};
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        int lo = 0, hi = n_views - 1;
-        while (lo < hi) {                  // last view with tile_off <= t
-            const int mid = (lo + hi + 1) >> 1;
-            if (views[mid].tile_off <= t) lo = mid; else hi = mid - 1;
-        }
+        const int lo = batch_view_of<&BatchView::tile_off>(views, n_views, t);
         const BatchView &v = views[lo];
         const int local = t - v.tile_off;
         const int ty = local / v.tiles_x, tx = local - ty * v.tiles_x;

@@ -75,13 +75,35 @@ struct BatchView {
     int32_t tiles_x;
     int32_t tile_off;   // exclusive prefix of filter tiles over the views
     int32_t n_tiles;
+    int32_t px_chunk_off;   // exclusive prefix of kBatchChunk-pixel chunks
+    int32_t pt_chunk_off;   // exclusive prefix of kBatchChunk-point chunks
 };
+
+// Elements (pixels or points) one workgroup handles per batch chunk.
+constexpr int kBatchChunk = 1024;
 
 struct BatchHeader {
     int32_t n_views;
     int32_t total_tiles;
-    int64_t pad;
+    int32_t px_chunks;
+    int32_t pt_chunks;
 };
+
+// Last view v with views[v].*field <= c (the fields are exclusive prefixes,
+// so v is the view that owns chunk or tile c). Wave-uniform arguments give
+// scalar loads.
+template <int32_t BatchView::*FIELD>
+__device__ inline int batch_view_of(const BatchView *views, int n_views, int c) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].*FIELD <= c)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
 hipError_t launch_batch(const void *d_table, int32_t max_radius,
                         jbfd_precision prec, hipStream_t s);

@@ -139,25 +139,44 @@ __global__ __launch_bounds__(256) void k_decode(const uint64_t *__restrict__ key
 // grid-stride over each view's pixels or points
 // ---------------------------------------------------------------------------
 
+// Each workgroup takes chunks of kBatchChunk elements; chunk c belongs to
+// the view found by a scalar binary search of the chunk prefixes, so every
+// view's work is spread over the whole grid at once.
+
 __global__ __launch_bounds__(256) void k_batch_clear(const BatchHeader *__restrict__ hdr,
                                                      const BatchView *__restrict__ views) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int v = 0; v < hdr->n_views; ++v) {
-        uint64_t *keys = views[v].zbuf;
-        const int64_t n = (int64_t)views[v].W * views[v].H;
-        for (int64_t i = tid; i < n; i += stride) keys[i] = kEmptyKey;
+    const int n_views = hdr->n_views, chunks = hdr->px_chunks;
+    for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const BatchView &bv =
+            views[batch_view_of<&BatchView::px_chunk_off>(views, n_views, c)];
+        const int64_t npix = (int64_t)bv.W * bv.H;
+        const int64_t p0 = (int64_t)(c - bv.px_chunk_off) * kBatchChunk +
+                           4 * (int64_t)threadIdx.x;
+        uint64_t *keys = bv.zbuf;
+        if ((reinterpret_cast<uintptr_t>(keys) & 15) == 0 && p0 + 4 <= npix) {
+            const ulonglong2 e = make_ulonglong2(kEmptyKey, kEmptyKey);
+            *reinterpret_cast<ulonglong2 *>(keys + p0) = e;
+            *reinterpret_cast<ulonglong2 *>(keys + p0 + 2) = e;
+        } else {
+            for (int64_t p = p0; p < npix && p < p0 + 4; ++p) keys[p] = kEmptyKey;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void k_batch_project(const BatchHeader *__restrict__ hdr,
                                                        const BatchView *__restrict__ views) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int v = 0; v < hdr->n_views; ++v) {
-        const BatchView &bv = views[v];
+    const int n_views = hdr->n_views, chunks = hdr->pt_chunks;
+    for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const BatchView &bv =
+            views[batch_view_of<&BatchView::pt_chunk_off>(views, n_views, c)];
         unsigned long long *keys = reinterpret_cast<unsigned long long *>(bv.zbuf);
-        for (int64_t i = tid; i < bv.n_pts; i += stride) {
+        const int64_t i0 = (int64_t)(c - bv.pt_chunk_off) * kBatchChunk + threadIdx.x;
+        // four points per thread, 256 apart (coalesced); every point's
+        // projection is independent, its atomic needs no result
+#pragma unroll
+        for (int j = 0; j < kBatchChunk / 256; ++j) {
+            const int64_t i = i0 + 256 * j;
+            if (i >= bv.n_pts) break;
             unsigned long long key;
             int64_t pix;
             if (project_one(bv.pts, i, bv.pose, bv.fx, bv.fy, bv.cx, bv.cy, bv.W,
@@ -169,14 +188,16 @@ __global__ __launch_bounds__(256) void k_batch_project(const BatchHeader *__rest
 
 __global__ __launch_bounds__(256) void k_batch_decode(const BatchHeader *__restrict__ hdr,
                                                       const BatchView *__restrict__ views) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int v = 0; v < hdr->n_views; ++v) {
-        const BatchView &bv = views[v];
+    const int n_views = hdr->n_views, chunks = hdr->px_chunks;
+    for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const BatchView &bv =
+            views[batch_view_of<&BatchView::px_chunk_off>(views, n_views, c)];
         const int64_t npix = (int64_t)bv.W * bv.H;
-        const bool vec = decode_vec_ok(bv.zbuf, bv.sd, bv.sv);
-        for (int64_t g = tid; g < (npix + 3) / 4; g += stride)
-            decode4(bv.zbuf, npix, g * 4, vec, bv.sd, bv.sv);
+        const int64_t p0 = (int64_t)(c - bv.px_chunk_off) * kBatchChunk +
+                           4 * (int64_t)threadIdx.x;
+        if (p0 < npix)
+            decode4(bv.zbuf, npix, p0, decode_vec_ok(bv.zbuf, bv.sd, bv.sv),
+                    bv.sd, bv.sv);
     }
 }
 
@@ -205,7 +226,7 @@ hipError_t launch_batch(const void *d_table, int32_t max_radius,
     const BatchHeader *hdr = static_cast<const BatchHeader *>(d_table);
     const BatchView *views = reinterpret_cast<const BatchView *>(
         static_cast<const unsigned char *>(d_table) + sizeof(BatchHeader));
-    const int grid = 1024;   // four workgroups per CU, grid-striding
+    const int grid = 2048;   // eight workgroups per CU, striding over chunks
     k_batch_clear<<<grid, 256, 0, s>>>(hdr, views);
     k_batch_project<<<grid, 256, 0, s>>>(hdr, views);
     k_batch_decode<<<grid, 256, 0, s>>>(hdr, views);

@@ -2,7 +2,7 @@
 
 Frames arrive from many viewpoints at their own clocks (mixed resolutions
 and point counts). The paper runs each viewpoint on its own PC with no
-exchange between them (Sec. 3); here all viewpoints share one GPU and the
+exchange between them (Sec. 2); here all viewpoints share one GPU and the
 loop keeps it busy:
 
 * **Slots** hold one frame's device buffers (points, RGB, z-buffer, sparse
@@ -202,6 +202,21 @@ class Server:
         self.batch_sizes: List[int] = []
         self.max_seen_inflight = 0
 
+    def prefill(self, keys: Sequence[tuple], per_key: int) -> None:
+        """Allocate up to ``per_key`` idle slots of each shape ahead of
+        time (within the budget), so the first frames do not pay for it."""
+        got = []
+        for key in keys:
+            for _ in range(per_key):
+                if not self.pool.fits_ever(key):
+                    break
+                s = self.pool.acquire(key)
+                if s is None:
+                    break
+                got.append((key, s))
+        for key, s in got:
+            self.pool.release(key, s)
+
     # -- one scheduling round -------------------------------------------
     def _complete(self, now: float) -> bool:
         progressed = False
@@ -293,7 +308,7 @@ class GpuExecutor:
 
     def __init__(self, device=None, precision=binding.Precision.FP16_RANGE,
                  max_batch: int = 16, max_inflight: int = 2,
-                 use_graphs: bool = True):
+                 use_graphs: bool = True, timing: bool = False):
         import torch
         self.torch = torch
         self.dev = torch.device(device if device is not None else "cuda:0")
@@ -312,6 +327,10 @@ class GpuExecutor:
         self.n_launch = 0
         self.use_graphs = use_graphs
         self.graphs: Dict[Tuple[int, int], object] = {}
+        # optional: HIP events around each batch's kernels on the compute
+        # stream; kernel_ms collects their durations at finish()
+        self.timing = timing
+        self.kernel_ms: List[float] = []
 
     # slots ---------------------------------------------------------------
     @staticmethod
@@ -393,10 +412,13 @@ class GpuExecutor:
         if self.host_events[k] is not None:
             self.host_events[k].synchronize()
         self.n_launch += 1
-        ev_c = torch.cuda.Event()
+        ev_c = torch.cuda.Event(enable_timing=self.timing)
+        ev_k = torch.cuda.Event(enable_timing=True) if self.timing else None
         with torch.cuda.stream(self.comp):
             self.comp.wait_event(ev_in)
             binding.batch_upload(views, self.table, host)
+            if ev_k is not None:
+                ev_k.record(self.comp)
             if graph is not None:
                 graph.replay()
             else:
@@ -410,31 +432,38 @@ class GpuExecutor:
                 slot.out_host.copy_(slot.view.dense_depth, non_blocking=True)
                 slot.mask_host.copy_(slot.view.dense_valid, non_blocking=True)
             ev_out.record(self.d2h)
-        return ev_out
+        return (ev_out, ev_k, ev_c)
 
     def done(self, handle) -> bool:
-        return handle.query()
+        return handle[0].query()
 
     def finish(self, handle) -> None:
-        handle.synchronize()
+        handle[0].synchronize()
+        if handle[1] is not None:
+            self.kernel_ms.append(handle[1].elapsed_time(handle[2]))
 
 
-def run_plain(requests: Sequence[Request], precision, device=None,
-              clock=time.perf_counter, sleep=time.sleep,
-              on_done: Optional[Callable[[Request, object, object], None]] = None,
-              lists: bool = True) -> List[Request]:
+class PlainRunner:
     """Per-frame baseline: each request in arrival order, alone on one
-    stream: copy in, jbfd_project, jbfd_densify, copy out, synchronise."""
-    import torch
-    dev = torch.device(device if device is not None else "cuda:0")
-    s = torch.cuda.Stream(dev)
-    bufs: Dict[tuple, dict] = {}
-    order = sorted(requests, key=lambda r: r.t_arrival)
-    for req in order:                         # buffers before the clock starts
-        k = req.vp.key
-        if k not in bufs:
-            w, h, n = k
-            bufs[k] = dict(
+    stream: copy in, jbfd_project, jbfd_densify, copy out, synchronise.
+    Buffers (one set per frame shape, resident on the device) are kept
+    between runs."""
+
+    def __init__(self, precision, device=None, lists: bool = True):
+        import torch
+        self.torch = torch
+        self.prec = precision
+        self.dev = torch.device(device if device is not None else "cuda:0")
+        self.stream = torch.cuda.Stream(self.dev)
+        self.lists = lists
+        self.bufs: Dict[tuple, dict] = {}
+
+    def _buffers(self, vp: Viewpoint) -> dict:
+        torch, dev = self.torch, self.dev
+        k = (vp.key, vp.radius)
+        if k not in self.bufs:
+            w, h, n = vp.key
+            self.bufs[k] = dict(
                 pts=torch.empty((n, 3), dtype=torch.float32, device=dev),
                 rgb=torch.empty((h, w, 3), dtype=torch.uint8, device=dev),
                 zbuf=torch.empty((h, w), dtype=torch.int64, device=dev),
@@ -442,29 +471,48 @@ def run_plain(requests: Sequence[Request], precision, device=None,
                 v=torch.empty((h, w), dtype=torch.uint8, device=dev),
                 out=torch.empty((h, w), dtype=torch.float32, device=dev),
                 mask=torch.empty((h, w), dtype=torch.uint8, device=dev),
-                ws=(binding.densify_workspace(h, w, req.vp.radius, n, dev)
-                    if lists else None),
+                ws=(binding.densify_workspace(h, w, vp.radius, n, dev)
+                    if self.lists else None),
                 out_h=torch.empty((h, w), dtype=torch.float32, pin_memory=True),
                 mask_h=torch.empty((h, w), dtype=torch.uint8, pin_memory=True))
-    torch.cuda.synchronize(dev)
-    t0 = clock()
-    for req in order:
-        while clock() - t0 < req.t_arrival:
-            sleep(max(0.0, min(50e-6, req.t_arrival - (clock() - t0))))
-        b, vp, n = bufs[req.vp.key], req.vp, int(req.n_points)
-        with torch.cuda.stream(s):
-            if n:
-                b["pts"][:n].copy_(req.points[:n], non_blocking=True)
-            b["rgb"].copy_(req.rgb, non_blocking=True)
-            binding.project(b["pts"][:n], vp.pose, vp.intrinsics, vp.width,
-                            vp.height, b["zbuf"], b["d"], b["v"])
-            binding.densify(b["d"], b["v"], b["rgb"], vp.radius, vp.sigma_s,
-                            vp.sigma_r, precision, b["out"], b["mask"],
-                            ws=b["ws"], max_samples=n)
-            b["out_h"].copy_(b["out"], non_blocking=True)
-            b["mask_h"].copy_(b["mask"], non_blocking=True)
-        s.synchronize()
-        req.t_done = clock() - t0
-        if on_done is not None:
-            on_done(req, b["out_h"], b["mask_h"])
-    return order
+        return self.bufs[k]
+
+    def run(self, requests: Sequence[Request], clock=time.perf_counter,
+            sleep=time.sleep,
+            on_done: Optional[Callable[[Request, object, object], None]] = None
+            ) -> List[Request]:
+        torch, s = self.torch, self.stream
+        order = sorted(requests, key=lambda r: r.t_arrival)
+        for req in order:                     # buffers before the clock starts
+            self._buffers(req.vp)
+        torch.cuda.synchronize(self.dev)
+        t0 = clock()
+        for req in order:
+            while clock() - t0 < req.t_arrival:
+                sleep(max(0.0, min(50e-6, req.t_arrival - (clock() - t0))))
+            b, vp, n = self._buffers(req.vp), req.vp, int(req.n_points)
+            with torch.cuda.stream(s):
+                if n:
+                    b["pts"][:n].copy_(req.points[:n], non_blocking=True)
+                b["rgb"].copy_(req.rgb, non_blocking=True)
+                binding.project(b["pts"][:n], vp.pose, vp.intrinsics, vp.width,
+                                vp.height, b["zbuf"], b["d"], b["v"])
+                binding.densify(b["d"], b["v"], b["rgb"], vp.radius,
+                                vp.sigma_s, vp.sigma_r, self.prec, b["out"],
+                                b["mask"], ws=b["ws"], max_samples=n)
+                b["out_h"].copy_(b["out"], non_blocking=True)
+                b["mask_h"].copy_(b["mask"], non_blocking=True)
+            s.synchronize()
+            req.t_done = clock() - t0
+            if on_done is not None:
+                on_done(req, b["out_h"], b["mask_h"])
+        return order
+
+
+def run_plain(requests: Sequence[Request], precision, device=None,
+              clock=time.perf_counter, sleep=time.sleep,
+              on_done: Optional[Callable[[Request, object, object], None]] = None,
+              lists: bool = True) -> List[Request]:
+    """One-off PlainRunner run over ``requests``."""
+    return PlainRunner(precision, device, lists).run(requests, clock, sleep,
+                                                     on_done)

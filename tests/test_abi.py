@@ -164,9 +164,12 @@ def test_batch_prepare_serialises_table(L):
     assert n > 16 and binding.batch_table_bytes(0) == 0
     host = np.zeros(n, np.uint8)
     binding.batch_prepare_raw(views, host)
-    hdr = host[:8].view(np.int32)
+    hdr = host[:16].view(np.int32)
     tiles = [((40 + k + 15) // 16) * ((30 + 2 * k + 15) // 16) for k in range(3)]
     assert hdr[0] == 3 and hdr[1] == sum(tiles)
+    # 1024-element chunks of pixels and of points, per view
+    assert hdr[2] == sum(-(-(40 + k) * (30 + 2 * k) // 1024) for k in range(3))
+    assert hdr[3] == 3 * -(-100 // 1024)
     # table too small
     with pytest.raises(binding.JbfdError) as e:
         binding.batch_prepare_raw(views, np.zeros(n - 8, np.uint8))
