@@ -98,9 +98,9 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_sigma(
     const uint32_t lxy = (uint32_t)(i + 2 * r + 7) | ((uint32_t)(py + r + 7) << 16);
     const uint32_t gstride = 4u | ((uint32_t)(4 * ts) << 16);
     const float kr2 = 2.0f * fp.kr;
-    const ListArgs none{nullptr, nullptr, nullptr, 0, 0};
+    const ListArgs none{nullptr, nullptr, 0};
     const BlockWalker bw{D, B, rgb, H, W, r, none, bx, by, lane, prg, pb0, lxy,
-                         gstride, reinterpret_cast<const unsigned char *>(G),
+                         gstride, 0u, ts, reinterpret_cast<const unsigned char *>(G),
                          recs[wid], nq2h[wid], -fp.ks};
 
     // the forward's weight of this (pixel, sample) pair

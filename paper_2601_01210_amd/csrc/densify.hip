@@ -8,27 +8,27 @@
 // valid samples of each window. On a LiDAR image only a few percent of the
 // pixels are valid, so no kernel here touches an invalid tap.
 //
-// Sample lists (with a caller workspace). Three small kernels build, once
-// per image, a row-sorted list of the valid samples of every 8-column strip
-// of the image, covering the strip's halo columns [8s-r, 8s+8+r):
-//   k_list_count    one workgroup per row: 64-bit validity masks of the row
-//                   (wave ballots) and, per strip, the row's sample count;
-//   k_list_scan     one workgroup per strip: exclusive scan of its row counts
-//                   and the strip total;
-//   k_list_scatter  one workgroup per row: scans the strip totals (workgroup
-//                   0 publishes them), then writes each valid sample into the
-//                   list of every strip whose halo holds it (rank inside the
-//                   row from the masks), as a 20-byte record
-//                   {x - (8s - r) | y << 16, (r,g) f16x2, (b,0) f16x2, depth,
-//                    -|rgb|^2 / 2}.
-// The halo of an 8x8 block is then one contiguous range of its strip's list.
-// The filter wave walks it in lockstep with scalar loads into SGPRs (every
-// lane needs the same record), so per sample there is no staging work and
-// no LDS traffic for the record: an LDS broadcast read would still move 16
-// bytes into each of the 64 lanes and make the filter LDS-bandwidth bound.
+// Sample lists (with a caller workspace). The image is cut into 8-column
+// strips; the list of strip s holds, sorted by row and then column, every
+// valid sample in the strip's halo columns [8s-r, 8s+8+r), as a 20-byte
+// record {(r,g) f16x2, (b,0) f16x2, depth, -|rgb|^2 / 2, table word}. Two
+// kernels build all lists, each over (group of 8 strips) x (band of 16
+// rows) units:
+//   k_list_count    validity masks of the band's rows over the group's 128
+//                   halo columns (wave ballots) -> records per strip and band;
+//   k_list_scatter  the group's strip offsets from the band counts, per-row
+//                   offsets by a wave scan over the band's rows (written
+//                   to rowoff), then every valid sample written into the list
+//                   of each strip of the group whose halo holds it (its rank
+//                   in the row from the masks).
+// The halo rows of an 8x8 block are one contiguous range of its strip's
+// list. The filter wave walks it in lockstep with scalar loads into SGPRs
+// (every lane needs the same record), so per sample there is no staging work
+// and no LDS traffic for the record: an LDS broadcast read would still move
+// 16 bytes into each of the 64 lanes and make the filter LDS-bandwidth
+// bound. A block whose range does not fit the workspace streams instead.
 //
-// Without a workspace (or if the caller's workspace is too small for the
-// lists), each wave instead streams the halo of its block from the input
+// Without a workspace each wave streams the halo of its block from the input
 // images in 64-pixel chunks and compacts the valid samples into a
 // wave-private LDS list (software-pipelined: the mask bytes of chunk c+2
 // and the sample data of chunk c+1 load while chunk c is processed).
@@ -36,22 +36,20 @@
 // Per sample and lane (one output pixel):
 //   colour   t = p.q - |q|^2/2 by two v_dot2_f32_f16 on the 0..255 channel
 //            values (every product and partial sum is an integer or
-//            half-integer below 2^23, so t is exact); -kr c = 2 kr t - kr|p|^2
-//            with the per-lane -kr|p|^2 folded into the shift M;
+//            half-integer below 2^23, so t is exact); -kr c = 2 kr t - kr|p|^2;
 //   space    a per-workgroup LDS table G[dy][dx] = -ks (dx^2+dy^2) inside the
-//            (2r+1)^2 window and -inf outside, indexed by one packed 16-bit
-//            subtract and one v_dot2_u32_u16, so the window test is free;
-//   weight   w = exp2(fma(2 kr, t, M) + G), kr and ks in log2 units.
-// M starts at 2^23 - kr|p|^2 (on the half-integer grid) and is lowered by
-// whole integers k whenever a weight exponent would exceed +12; the
-// accumulators are then scaled by the exact power of two 2^-k and the
-// exponent is recomputed. Every weight of one pixel is thus its true value
-// times one common factor, which cancels in num/den; the largest weight of a
-// pixel lies in [2^-1, 2^12], so nothing underflows however far the colours
-// are, and because M only moves by exact integer steps the fma returns each
-// exponent with one rounding relative to the exponent itself. Epilogue:
-// out = num/den and mask = (den > 0), den being at least 1/2 once one sample
-// of the window was seen, so the mask is exact.
+//            (2r+1)^2 window and -inf outside; a list record carries its
+//            position as a table offset, so the lane's address is one
+//            subtract and the window test is free;
+//   weight   w = exp2(max(2 kr t - kr|p|^2, -60) + G), kr and ks in log2
+//            units (the table is clamped at -60 too), so every in-window
+//            sample has w >= 2^-120 > 0 and den > 0 is exactly the mask.
+// Lanes whose weight sum ends below 2^-16 (far colours: clamping or
+// rounding could matter) are recomputed in a second pass with an exact
+// running shift M: it starts at 2^23 - kr|p|^2 and drops by whole integers k
+// whenever an exponent would exceed +12, scaling the sums by 2^-k, with
+// unclamped spatial exponents. Every weight of a pixel is thus its true
+// value times one common factor, which cancels in num/den.
 //
 // The fraction of (pixel, halo sample) pairs that fall inside the window is
 // (2r+1)^2/(2r+8)^2 (66% at r = 15).
@@ -64,139 +62,264 @@ size_t densify_ws_bytes(int32_t H, int32_t W, int32_t r, int64_t max_samples) {
     return L.recs + (size_t)max_samples * strips_per_column(r) * kRecWords * 4;
 }
 
-__global__ __launch_bounds__(256) void k_list_count(
-    const uint8_t *__restrict__ B, int H, int W, int r, int n_strips,
-    int nwords, uint64_t *__restrict__ rowbits, int *__restrict__ counts) {
-    __shared__ uint64_t bits[512];
-    const int y = blockIdx.x;
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint8_t *row = B + (int64_t)y * W;
-    // eight 256-pixel slices per round, all loads issued before any ballot
-    for (int x0 = 0; x0 < W; x0 += 8 * 256) {
-        uint8_t v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int x = x0 + 256 * k + threadIdx.x;
-            v[k] = x < W ? row[x] : (uint8_t)0;
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint64_t bal = __builtin_amdgcn_ballot_w64(v[k] != 0);
-            const int xw = x0 + 256 * k + 64 * wid;
-            if (lane == 0 && xw < W) bits[xw >> 6] = bal;
-        }
-    }
-    __syncthreads();
-    for (int w = threadIdx.x; w < nwords; w += 256)
-        rowbits[(int64_t)y * nwords + w] = bits[w];
-    for (int s = threadIdx.x; s < n_strips; s += 256) {
-        const int a = max(8 * s - r, 0), b = min(8 * s + 8 + r, W);
-        counts[(int64_t)s * H + y] = popc_range(bits, a, b);
-    }
-}
-
-// inclusive scan across the 64 lanes of a wave
-__device__ inline int wave_inclusive_scan(int v) {
+// Load the validity bytes of rows [y_first, y_first + n) over the group's
+// 128 halo columns [c0, c0 + 128) and ballot them into 128-bit row masks
+// (columns outside the image read as invalid). All loads are issued before
+// the first ballot.
+template <int NROWS>
+__device__ inline void group_row_masks(const uint8_t *__restrict__ B, int H, int W,
+                                       int c0, int y_first, uint64_t (&lo)[NROWS],
+                                       uint64_t (&hi)[NROWS]) {
     const int lane = threadIdx.x & 63;
+    const int xa = c0 + lane, xb = c0 + 64 + lane;
+    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
+    // every load is unconditional from a clamped (in-image) address, so all
+    // of them are in flight together; out-of-image lanes are masked after
+    const int xa_c = min(max(xa, 0), W - 1), xb_c = min(max(xb, 0), W - 1);
+    uint8_t va[NROWS], vb[NROWS];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
+    for (int k = 0; k < NROWS; ++k) {
+        const uint8_t *row = B + (int64_t)min(y_first + k, H - 1) * W;
+        va[k] = row[xa_c];
+        vb[k] = row[xb_c];
     }
-    return v;
+#pragma unroll
+    for (int k = 0; k < NROWS; ++k) {
+        const bool iny = y_first + k < H;
+        lo[k] = __builtin_amdgcn_ballot_w64(ina && iny && va[k] != 0);
+        hi[k] = __builtin_amdgcn_ballot_w64(inb && iny && vb[k] != 0);
+    }
 }
 
-// Exclusive scan of n ints in place by one 256-thread workgroup: every
-// thread sums a contiguous segment, one workgroup scan of the 256 sums, then
-// every thread rewrites its segment. Returns the total.
-__device__ inline int segment_scan(int *__restrict__ a, int n, int *wsum) {
-    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int seg = (n + 255) / 256;
-    const int b0 = min(t * seg, n), b1 = min(b0 + seg, n);
-    int sum = 0;
-    for (int i0 = b0; i0 < b1; i0 += 8) {
-        int v[8];
+// Records per (strip, band): workgroup (group g, band b); wave w ballots a
+// quarter of the band's rows; lanes 0..7 count the rows' samples in the
+// halo of strip 8g + lane.
+__global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ B,
+                                                    int H, int W, int r, int n_strips,
+                                                    int n_bands,
+                                                    int *__restrict__ bandcnt,
+                                                    int *__restrict__ grpcnt) {
+    __shared__ int part[4][kGroupStrips];
+    const int g = blockIdx.x, band = blockIdx.y;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int c0 = 64 * g - r;
+    constexpr int kRowsPerWave = kBandRows / 4;
+    uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
+    group_row_masks<kRowsPerWave>(B, H, W, c0, band * kBandRows + wid * kRowsPerWave,
+                                  lo, hi);
+    int acc = 0;
+    if (lane < kGroupStrips) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = i0 + u < b1 ? a[i0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) sum += v[u];
+        for (int k = 0; k < kRowsPerWave; ++k)
+            acc += popc128(lo[k], hi[k], 8 * lane, 8 * lane + 8 + 2 * r);
+        part[wid][lane] = acc;
     }
-    const int incl = wave_inclusive_scan(sum);
-    if (lane == 63) wsum[wid] = incl;
     __syncthreads();
-    int before = 0, total = 0;
-    for (int w = 0; w < 4; ++w) {
-        before += w < wid ? wsum[w] : 0;
-        total += wsum[w];
+    if (threadIdx.x < 64) {   // wave 0: strips of the group, then their sum
+        const int q = threadIdx.x;
+        const int s = kGroupStrips * g + q;
+        int sum = 0;
+        if (q < kGroupStrips && s < n_strips) {
+            sum = part[0][q] + part[1][q] + part[2][q] + part[3][q];
+            bandcnt[(int64_t)s * n_bands + band] = sum;
+        }
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 8);
+        if (q == 0) grpcnt[(int64_t)g * n_bands + band] = sum;
     }
-    int run = before + incl - sum;
-    for (int i0 = b0; i0 < b1; i0 += 8) {
-        int v[8];
+}
+
+// Offsets and records of the group's strips over one band (see the file
+// comment). The absolute start of strip s is the sum of the band counts of
+// every strip before it; the start of band b within s adds the counts of
+// bands < b.
+__global__ __launch_bounds__(256) void k_list_scatter(
+    const float *__restrict__ D, const uint8_t *__restrict__ B,
+    const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
+    int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
+    int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs) {
+    __shared__ uint64_t mlo[kBandRows], mhi[kBandRows];
+    __shared__ __align__(16) int start[kBandRows][kGroupStrips];   // [row][strip]
+    __shared__ int rowpos[kBandRows + 1];
+    __shared__ uint16_t plist[kBandRows * 128];   // valid pixels of the band
+
+    __shared__ int red[4];
+    __shared__ int stot[kGroupStrips], spre[kGroupStrips], sbase[kGroupStrips];
+    const int g = blockIdx.x, band = blockIdx.y;
+    const int t = threadIdx.x;
+    const int wid = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    const int c0 = 64 * g - r;
+    const int y_band = band * kBandRows;
+    const int s_first = kGroupStrips * g;
+
+    // (1) records of all strips before the group: the group-and-band
+    // totals of groups < g (the first g*n_bands entries of grpcnt)
+    int acc = 0;
+    const int n_before = g * n_bands;
+    for (int k0 = 0; k0 < n_before; k0 += 2 * 256) {
+        const int a0 = k0 + t < n_before ? grpcnt[k0 + t] : 0;
+        const int a1 = k0 + 256 + t < n_before ? grpcnt[k0 + 256 + t] : 0;
+        acc += a0 + a1;
+    }
+    // (2) per strip of the group: total and the part in bands before ours
+    //     (32 threads per strip)
+    const int j = t >> 5, k32 = t & 31;
+    const int sj = s_first + j;
+    int tot = 0, pre = 0;
+    if (sj < n_strips) {
+        for (int b = k32; b < n_bands; b += 32) {
+            const int c = bandcnt[(int64_t)sj * n_bands + b];
+            tot += c;
+            pre += b < band ? c : 0;
+        }
+    }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = i0 + u < b1 ? a[i0 + u] : 0;
+    for (int off = 16; off > 0; off >>= 1) {
+        tot += __shfl_xor(tot, off, 32);
+        pre += __shfl_xor(pre, off, 32);
+    }
+    if (k32 == 0) {
+        stot[j] = tot;
+        spre[j] = pre;
+    }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (i0 + u < b1) a[i0 + u] = run;
-            run += v[u];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) red[wid] = acc;
+    // (3) validity masks of the band's rows (wave w: rows 16w .. 16w+15)
+    {
+        constexpr int kRowsPerWave = kBandRows / 4;
+        uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
+        group_row_masks<kRowsPerWave>(B, H, W, c0, y_band + wid * kRowsPerWave, lo, hi);
+        if (lane < kRowsPerWave) {
+            uint64_t a = 0, b = 0;
+#pragma unroll
+            for (int k = 0; k < kRowsPerWave; ++k) {
+                a = lane == k ? lo[k] : a;
+                b = lane == k ? hi[k] : b;
+            }
+            mlo[wid * kRowsPerWave + lane] = a;
+            mhi[wid * kRowsPerWave + lane] = b;
         }
     }
     __syncthreads();
-    return total;
-}
-
-__global__ __launch_bounds__(256) void k_list_scan(int *__restrict__ rowoff,
-                                                   int H,
-                                                   int *__restrict__ totals) {
-    __shared__ int wsum[4];
-    const int s = blockIdx.x;
-    const int total = segment_scan(rowoff + (int64_t)s * H, H, wsum);
-    if (threadIdx.x == 0) totals[s] = total;
-}
-
-__global__ __launch_bounds__(256) void k_list_scatter(
-    const float *__restrict__ D, const uint8_t *__restrict__ rgb, int H, int W,
-    int r, int n_strips, int nwords, const uint64_t *__restrict__ rowbits,
-    const int *__restrict__ rowoff, const int *__restrict__ totals,
-    int *__restrict__ base, int64_t capacity, uint32_t *__restrict__ recs) {
-    __shared__ uint64_t bits[512];
-    __shared__ int start[4097];   // strip offsets, then this row's first index
-    __shared__ int wsum[4];
-    const int y = blockIdx.x;
-    // every workgroup scans the strip totals (at most 4096 ints) itself;
-    // workgroup 0 publishes them for the filter
-    for (int t = threadIdx.x; t < n_strips; t += 256) start[t] = totals[t];
-    for (int w = threadIdx.x; w < nwords; w += 256)
-        bits[w] = rowbits[(int64_t)y * nwords + w];
-    __syncthreads();
-    const int all = segment_scan(start, n_strips, wsum);
-    if (y == 0) {
-        for (int t = threadIdx.x; t < n_strips; t += 256) base[t] = start[t];
-        if (threadIdx.x == 0) base[n_strips] = all;
+    if (t == 0) {
+        int run = red[0] + red[1] + red[2] + red[3];
+        for (int q = 0; q < kGroupStrips; ++q) {
+            sbase[q] = run + spre[q];
+            run += stot[q];
+        }
     }
-    if (all > capacity) return;   // lists do not fit: not used
-    for (int t = threadIdx.x; t < n_strips; t += 256)
-        start[t] += rowoff[(int64_t)t * H + y];
+    // (4) per-row counts of each strip of the group
+    for (int e = t; e < kGroupStrips * kBandRows; e += 256) {
+        const int q = e / kBandRows, row = e % kBandRows;
+        start[row][q] = popc128(mlo[row], mhi[row], 8 * q, 8 * q + 8 + 2 * r);
+    }
     __syncthreads();
-    for (int x = threadIdx.x; x < W; x += 256) {
-        if (!((bits[x >> 6] >> (x & 63)) & 1ull)) continue;
-        const int64_t p = (int64_t)y * W + x;
-        const uint8_t *c = rgb + 3 * p;
-        uint32_t rg, b0;
-        float nq2h;
-        colour_fields((uint32_t)c[0] | ((uint32_t)c[1] << 8), c[2], rg, b0, nq2h);
-        const float d = D[p];
-        const int n = x - r - 7;
-        const int s_lo = n > 0 ? (n + 7) / 8 : 0;
-        const int s_hi = min((x + r) / 8, n_strips - 1);
-        for (int s = s_lo; s <= s_hi; ++s) {
-            const int a = max(8 * s - r, 0);
-            const int64_t idx = (int64_t)start[s] + popc_range(bits, a, x);
-            uint32_t *q = recs + idx * kRecWords;
-            q[0] = (uint32_t)(x - (8 * s - r)) | ((uint32_t)y << 16);
-            q[1] = rg;
-            q[2] = b0;
-            q[3] = __float_as_uint(d);
-            q[4] = __float_as_uint(nq2h);
+    // (5) exclusive scan over the band's rows (lane = row): wave w scans
+    // strips w, w + 4
+    for (int q = wid; q < kGroupStrips; q += 4) {
+        const bool rl = lane < kBandRows;
+        const int v = rl ? start[rl ? lane : 0][q] : 0;
+        const int incl = wave_inclusive_scan(v);
+        const int st = sbase[q] + incl - v;
+        if (rl) start[lane][q] = st;
+        const int s = s_first + q;
+        const int y = y_band + lane;
+        if (s < n_strips) {
+            int *ro = rowoff + (int64_t)s * (H + 1);
+            if (rl && y < H) ro[y] = st;
+            if (band == n_bands - 1 && lane == 0)
+                ro[H] = sbase[q] - spre[q] + stot[q];   // end of strip s
+        }
+    }
+    __syncthreads();
+    // (6) compact the band's valid pixels into plist (row << 8 | column),
+    // row by row: rowpos is the exclusive prefix of the rows' counts
+    if (wid == 0) {
+        const bool rl = lane < kBandRows;
+        const int row = rl ? lane : 0;
+        const int cnt = rl ? __builtin_popcountll(mlo[row]) + __builtin_popcountll(mhi[row])
+                           : 0;
+        const int incl = wave_inclusive_scan(cnt);
+        if (rl) rowpos[lane] = incl - cnt;
+        if (lane == 63) rowpos[kBandRows] = incl;
+    }
+    __syncthreads();
+    for (int row = wid; row < kBandRows; row += 4) {
+        const uint64_t ml = mlo[row], mh = mhi[row];
+        const int base = rowpos[row];
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(ml >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ml, 0u));
+        if ((ml >> lane) & 1ull) plist[base + below] = (uint16_t)((row << 8) | lane);
+        const uint32_t below_h =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(mh >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mh, 0u));
+        if ((mh >> lane) & 1ull)
+            plist[base + __builtin_popcountll(ml) + below_h] =
+                (uint16_t)((row << 8) | (64 + lane));
+    }
+    __syncthreads();
+    // (7) one thread per valid pixel (two per pass): load its colour and
+    // depth, then write its record into each strip of the group whose halo
+    // holds it
+    const int ts = table_stride(r);
+    const int total = rowpos[kBandRows];
+    const int n_here = min(kGroupStrips, n_strips - s_first);
+    for (int e0 = 0; e0 < total; e0 += 512) {
+        int ent[2];
+        bool ok[2];
+        uint32_t c01[2], c2[2], dd[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + 256 * u + t;
+            ok[u] = e < total;
+            ent[u] = plist[ok[u] ? e : 0];     // entry 0 exists: total > 0
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = ent[u] >> 8, lc = ent[u] & 255;
+            const int64_t p = (int64_t)(y_band + row) * W + (c0 + lc);
+            const uint8_t *c = rgb + 3 * p;
+            c01[u] = (uint32_t)c[0] | ((uint32_t)c[1] << 8);
+            c2[u] = c[2];
+            dd[u] = __float_as_uint(D[p]);
+        }
+        // wait for these loads once, here: the store counter is the same
+        // in-order counter as the load counter, so a load still pending at a
+        // store (the depth word is stored as loaded) would make every record
+        // store wait for all earlier ones
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt/lgkmcnt any
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!ok[u]) continue;
+            const int row = ent[u] >> 8, lc = ent[u] & 255;
+            const int y = y_band + row;
+            uint32_t rg, b0;
+            float nq2h;
+            colour_fields(c01[u], c2[u], rg, b0, nq2h);
+            const uint64_t ml = mlo[row], mh = mhi[row];
+            const int4 sa = *reinterpret_cast<const int4 *>(&start[row][0]);
+            const int4 sb = *reinterpret_cast<const int4 *>(&start[row][4]);
+            const int st[kGroupStrips] = {sa.x, sa.y, sa.z, sa.w,
+                                          sb.x, sb.y, sb.z, sb.w};
+#pragma unroll
+            for (int q = 0; q < kGroupStrips; ++q) {
+                // strips q of the group with 8q <= lc < 8q + 8 + 2r
+                if (q >= n_here || lc < 8 * q || lc >= 8 * q + 8 + 2 * r) continue;
+                const int64_t idx = (int64_t)st[q] + popc128(ml, mh, 8 * q, lc);
+                if (idx >= capacity) continue;
+                // words 0-3 are the same for every strip of this sample, so
+                // their (merged) store never waits on a rewritten register
+                uint32_t *o = recs + idx * kRecWords;
+                o[0] = rg;
+                o[1] = b0;
+                o[2] = dd[u];
+                o[3] = __float_as_uint(nq2h);
+                o[4] = rec_table_word(lc - 8 * q, y, ts);
+            }
         }
     }
 }
@@ -254,8 +377,11 @@ __device__ void filter_tile(const float *__restrict__ D,
     const uint32_t lxy = (uint32_t)(i + 2 * r + 7) | ((uint32_t)(py + r + 7) << 16);
     const uint32_t gstride = 4u | ((uint32_t)(4 * ts) << 16);
     const float kr2 = 2.0f * fp.kr;
+    const uint32_t lc =
+        4u * ((uint32_t)(i + 2 * r + 7) + (uint32_t)ts * (uint32_t)(py + r + 7));
     const BlockWalker bw{D, B, rgb, H, W, r, la, bx, by, lane, prg, pb0, lxy,
-                         gstride, reinterpret_cast<const unsigned char *>(sh.G),
+                         gstride, lc, ts,
+                         reinterpret_cast<const unsigned char *>(sh.G),
                          sh.recs[wid], sh.nq2h[wid], -fp.ks};
 
     // Pass 1: fixed per-lane shift. Every exponent E = -kr c - ks s is <= 0,
@@ -358,13 +484,14 @@ hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
                                   hipStream_t s) {
     const ListLayout L = list_layout(H, W);
     ListViews v;
-    if (!list_views(ws, ws_bytes, L, v)) return hipSuccess;  // nothing to build
-    k_list_count<<<H, 256, 0, s>>>(B, H, W, radius, L.n_strips, L.nwords,
-                                   v.rowbits, v.rowoff);
-    k_list_scan<<<L.n_strips, 256, 0, s>>>(v.rowoff, H, v.totals);
-    k_list_scatter<<<H, 256, 0, s>>>(D, rgb, H, W, radius, L.n_strips, L.nwords,
-                                     v.rowbits, v.rowoff, v.totals, v.base,
-                                     v.capacity, v.recs);
+    if (!lists_possible(H, W, radius) || !list_views(ws, ws_bytes, L, v))
+        return hipSuccess;  // nothing to build
+    const dim3 grid(L.n_groups, L.n_bands);
+    k_list_count<<<grid, 256, 0, s>>>(B, H, W, radius, L.n_strips, L.n_bands,
+                                      v.bandcnt, v.grpcnt);
+    k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, radius, L.n_strips,
+                                        L.n_bands, v.bandcnt, v.grpcnt, v.rowoff,
+                                        v.capacity, v.recs);
     return hipGetLastError();
 }
 
@@ -377,16 +504,16 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
     const int tiles_y = (H + kTile - 1) / kTile;
     const int n_tiles = tiles_x * tiles_y;
     const int n_pad = (n_tiles + 7) & ~7;
-    ListArgs la{nullptr, nullptr, nullptr, 0, 0};
+    ListArgs la{nullptr, nullptr, 0};
     const ListLayout L = list_layout(H, W);
     ListViews v;
-    if (list_views(ws, ws_bytes, L, v)) {
+    if (lists_possible(H, W, fp.radius) && list_views(ws, ws_bytes, L, v)) {
         if (!lists_ready) {
             const hipError_t e =
                 launch_densify_prepare(D, B, rgb, H, W, fp.radius, ws, ws_bytes, s);
             if (e != hipSuccess) return e;
         }
-        la = ListArgs{v.recs, v.rowoff, v.base, v.capacity, L.n_strips};
+        la = ListArgs{v.recs, v.rowoff, v.capacity};
     }
     float2 *a2 = reinterpret_cast<float2 *>(aux);
     const bool small = fp.radius <= 16;
@@ -421,7 +548,7 @@ __global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restr
     __shared__ FilterShared<RMAX> sh;
     const int n_views = hdr->n_views;
     const int total = hdr->total_tiles;
-    const ListArgs none{nullptr, nullptr, nullptr, 0, 0};
+    const ListArgs none{nullptr, nullptr, 0};
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int lo = batch_view_of<&BatchView::tile_off>(views, n_views, t);
         const BatchView &v = views[lo];

@@ -68,68 +68,65 @@ __device__ inline int xcd_tile(int wg, int n_pad) {
     return (wg & 7) * (n_pad >> 3) + (wg >> 3);
 }
 
-// number of set bits of the row mask `words` at positions [a, b)
-__device__ inline int popc_range(const uint64_t *words, int a, int b) {
-    if (b <= a) return 0;
-    const int wa = a >> 6, wb = (b - 1) >> 6;
-    int cnt = 0;
-    for (int w = wa; w <= wb; ++w) {
-        uint64_t m = words[w];
-        if (w == wa) m &= ~0ull << (a & 63);
-        const int hi = (b - 1) & 63;
-        if (w == wb && hi != 63) m &= (1ull << (hi + 1)) - 1ull;
-        cnt += __builtin_popcountll(m);
-    }
-    return cnt;
+// bits [a, b) of a 64-bit word (a, b clamped to [0, 64])
+__device__ inline uint64_t bit_range(int a, int b) {
+    a = max(a, 0);
+    b = min(b, 64);
+    if (b <= a) return 0ull;
+    const uint64_t hi = b == 64 ? ~0ull : ((1ull << b) - 1ull);
+    return hi & (~0ull << a);
 }
 
-// exclusive scan over the 256 threads of a workgroup (Hillis-Steele in LDS)
-__device__ inline int block_exclusive_scan(int v, int *scratch, int &total) {
-    const int t = threadIdx.x;
-    scratch[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int add = t >= off ? scratch[t - off] : 0;
-        __syncthreads();
-        scratch[t] += add;
-        __syncthreads();
-    }
-    const int incl = scratch[t];
-    total = scratch[255];
-    __syncthreads();
-    return incl - v;
+// number of set bits at positions [a, b) of the 128-bit mask (lo | hi << 64)
+__device__ inline int popc128(uint64_t lo, uint64_t hi, int a, int b) {
+    return __builtin_popcountll(lo & bit_range(a, b)) +
+           __builtin_popcountll(hi & bit_range(a - 64, b - 64));
 }
 
+// inclusive scan across the 64 lanes of a wave
+__device__ inline int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
 
 // ---------------------------------------------------------------------------
 // workspace layout of the sample lists
 // ---------------------------------------------------------------------------
 
+// The lists are built per (group of 8 strips) x (band of 16 rows).
+constexpr int kGroupStrips = 8;
+constexpr int kBandRows = 16;
+
 struct ListLayout {
-    int nwords;      // 64-bit mask words per row
-    int n_strips;
-    size_t rowbits;  // uint64 [H][nwords]
-    size_t rowoff;   // int32  [n_strips][H]   counts, then row offsets
-    size_t totals;   // int32  [n_strips]
-    size_t base;     // int32  [n_strips + 1]
-    size_t recs;     // uint32 [capacity][5]
+    int n_strips;    // 8-column strips
+    int n_groups;    // groups of kGroupStrips strips (64 columns)
+    int n_bands;     // bands of kBandRows rows
+    size_t rowoff;   // int32 [n_strips][H + 1]: absolute index of the first
+                     //   record of row y in strip s; [s][H] = end of strip s
+    size_t bandcnt;  // int32 [n_strips][n_bands]: records per strip and band
+    size_t grpcnt;   // int32 [n_groups][n_bands]: records per group and band
+    size_t recs;     // uint32 [capacity][kRecWords]
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline ListLayout list_layout(int H, int W) {
     ListLayout L;
-    L.nwords = (W + 63) / 64;
     L.n_strips = (W + 7) / 8;
+    L.n_groups = (L.n_strips + kGroupStrips - 1) / kGroupStrips;
+    L.n_bands = (H + kBandRows - 1) / kBandRows;
     size_t off = 0;
-    L.rowbits = off;
-    off = align256(off + (size_t)H * L.nwords * 8);
     L.rowoff = off;
-    off = align256(off + (size_t)L.n_strips * H * 4);
-    L.totals = off;
-    off = align256(off + (size_t)L.n_strips * 4);
-    L.base = off;
-    off = align256(off + (size_t)(L.n_strips + 1) * 4);
+    off = align256(off + (size_t)L.n_strips * (H + 1) * 4);
+    L.bandcnt = off;
+    off = align256(off + (size_t)L.n_strips * L.n_bands * 4);
+    L.grpcnt = off;
+    off = align256(off + (size_t)L.n_groups * L.n_bands * 4);
     L.recs = off;
     return L;
 }
@@ -137,12 +134,16 @@ inline ListLayout list_layout(int H, int W) {
 // Largest number of strips whose halo columns hold one image column.
 inline int strips_per_column(int r) { return (2 * r + 7) / 8 + 1; }
 
+// Record indices are int32: lists are built only when every pixel of the
+// image could be valid without overflowing them.
+inline bool lists_possible(int H, int W, int r) {
+    return (int64_t)H * W * strips_per_column(r) < ((int64_t)1 << 31);
+}
+
 struct ListArgs {
     const uint32_t *recs;   // nullptr: stream the halo instead
-    const int *rowoff;
-    const int *base;
-    int64_t capacity;
-    int n_strips;
+    const int *rowoff;      // [n_strips][H + 1]
+    int64_t capacity;       // records the workspace holds
 };
 
 // Consume four samples: exponents a = fma(2kr, t, M) + g, rescale when one
@@ -195,8 +196,7 @@ __device__ inline void consume1(float t, float g, float d, float kr2, float &M,
 
 // views of a caller workspace
 struct ListViews {
-    uint64_t *rowbits;
-    int *rowoff, *totals, *base;
+    int *rowoff, *bandcnt, *grpcnt;
     uint32_t *recs;
     int64_t capacity;
 };
@@ -205,26 +205,22 @@ inline bool list_views(void *ws, size_t ws_bytes, const ListLayout &L,
                        ListViews &v) {
     if (ws == nullptr || ws_bytes < L.recs) return false;
     unsigned char *w = static_cast<unsigned char *>(ws);
-    v.rowbits = reinterpret_cast<uint64_t *>(w + L.rowbits);
     v.rowoff = reinterpret_cast<int *>(w + L.rowoff);
-    v.totals = reinterpret_cast<int *>(w + L.totals);
-    v.base = reinterpret_cast<int *>(w + L.base);
+    v.bandcnt = reinterpret_cast<int *>(w + L.bandcnt);
+    v.grpcnt = reinterpret_cast<int *>(w + L.grpcnt);
     v.recs = reinterpret_cast<uint32_t *>(w + L.recs);
     v.capacity = (int64_t)((ws_bytes - L.recs) / (kRecWords * 4));
     return true;
 }
 
-// ---------------------------------------------------------------------------
-// Walking the valid samples of one 8x8 block's halo
-// ---------------------------------------------------------------------------
+// Last word of a list record {(r,g) f16x2, (b,0) f16x2, depth, -|q|^2/2,
+// table word}: the sample's byte offset in the spatial table frame,
+// 4 (x - (8s - r)) + 4 ts y, so that a lane's table byte address is its own
+// constant minus this word (one subtract per sample).
+__device__ inline uint32_t rec_table_word(int xrel, int y, int ts) {
+    return 4u * ((uint32_t)xrel + (uint32_t)ts * (uint32_t)y);
+}
 
-// One wave's view of its 8x8 output block. walk() visits every valid sample
-// of the block's halo, in row-major order, four at a time where it can, and
-// hands each consumer t = p.q - |q|^2/2 (p: this lane's colour, q: the
-// sample's), the spatial term g (from the LDS table, or exactly), the
-// sample's depth d and the packed offset u = (dx + r + 7, dy + r + 7).
-// Samples come from the per-strip list (scalar loads) when one is present,
-// else the wave streams its halo from the input images into LDS.
 struct BlockWalker {
     const float *D;
     const uint8_t *B;
@@ -235,6 +231,9 @@ struct BlockWalker {
     uint32_t prg, pb0;     // this lane's colour fields
     uint32_t lxy;          // (i + 2r + 7) | (py + r + 7) << 16
     uint32_t gstride;      // byte strides of the table index
+    uint32_t lc;           // 4 ((i + 2r + 7) + ts (py + r + 7)): table byte
+                           // address of a list record = lc - record word 0
+    int ts;                // table row stride (floats)
     const unsigned char *Gb;
     Rec *my;               // the wave's LDS list
     float *myq;
@@ -281,47 +280,67 @@ struct BlockWalker {
         }
     }
 
+    // table word of a list sample -> (ux | uy << 16) for the exact pass
+    __device__ uint32_t uv_of_offset(uint32_t off) const {
+        const int idx = (int)(off >> 2);
+        const int uy = (int)(((float)idx + 0.5f) * (1.0f / (float)ts));
+        const int ux = idx - uy * ts;
+        return (uint32_t)ux | ((uint32_t)uy << 16);
+    }
+
+    // records [lo, hi) of the strip list, read four at a time with scalar
+    // loads (every lane needs the same record)
+    template <bool EXACT, class E4, class E1>
+    __device__ void walk_list(int lo, int hi, E4 &eat4, E1 &eat1) const {
+        const uint32_t *__restrict__ rp = la.recs;
+        auto sample = [&](const uint32_t *q, float &t, float &g, float &d,
+                          uint32_t &uv) {
+            t = dot2h(prg, q[0], dot2h(pb0, q[1], __uint_as_float(q[3])));
+            const uint32_t off = lc - q[4];
+            if constexpr (EXACT) {
+                uv = uv_of_offset(off);
+                g = exact_g(uv);
+            } else {
+                uv = off;
+                g = *reinterpret_cast<const float *>(Gb + off);
+            }
+            d = __uint_as_float(q[2]);
+        };
+        int k = lo;
+        for (; k + 4 <= hi; k += 4) {
+            uint32_t q[4 * kRecWords];
+            const uint32_t *src = rp + (int64_t)k * kRecWords;
+#pragma unroll
+            for (int e = 0; e < 4 * kRecWords; ++e) q[e] = src[e];
+            float t[4], g[4], d[4];
+            uint32_t uv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                sample(q + u * kRecWords, t[u], g[u], d[u], uv[u]);
+            eat4(t, g, d, uv);
+        }
+        for (; k < hi; ++k) {
+            float t, g, d;
+            uint32_t uv;
+            sample(rp + (int64_t)k * kRecWords, t, g, d, uv);
+            eat1(t, g, d, uv);
+        }
+    }
+
     template <bool EXACT, class E4, class E1>
     __device__ void walk(E4 &&eat4, E1 &&eat1) const {
-        const bool lists = la.recs != nullptr &&
-                           (int64_t)la.base[la.n_strips] <= la.capacity;
-        if (lists) {
-            // the range [lo, hi) of the strip list, read with scalar loads
-            // (the records are the same for every lane), four at a time
+        if (la.recs != nullptr) {
+            // the range [lo, hi) of the strip list; it is used only when the
+            // whole range lies inside the workspace (else stream below)
             const int s = bx >> 3;
-            const int *ro = la.rowoff + (int64_t)s * H;
-            const int y0 = max(by - r, 0), y1 = by + 8 + r;
-            const int lo = __builtin_amdgcn_readfirstlane(la.base[s] + ro[y0]);
-            const int hi = __builtin_amdgcn_readfirstlane(
-                y1 < H ? la.base[s] + ro[y1] : la.base[s + 1]);
-            const uint32_t *__restrict__ rp = la.recs;
-            auto sample = [&](const uint32_t *q, float &t, float &g, float &d,
-                              uint32_t &uv) {
-                t = dot2h(prg, q[1], dot2h(pb0, q[2], __uint_as_float(q[4])));
-                uv = pk_sub_u16(lxy, q[0]);
-                g = spatial<EXACT>(uv);
-                d = __uint_as_float(q[3]);
-            };
-            int k = lo;
-            for (; k + 4 <= hi; k += 4) {
-                uint32_t q[4 * kRecWords];
-                const uint32_t *src = rp + (int64_t)k * kRecWords;
-#pragma unroll
-                for (int e = 0; e < 4 * kRecWords; ++e) q[e] = src[e];
-                float t[4], g[4], d[4];
-                uint32_t uv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    sample(q + u * kRecWords, t[u], g[u], d[u], uv[u]);
-                eat4(t, g, d, uv);
+            const int *ro = la.rowoff + (int64_t)s * (H + 1);
+            const int y0 = max(by - r, 0), y1 = min(by + 8 + r, H);
+            const int lo = __builtin_amdgcn_readfirstlane(ro[y0]);
+            const int hi = __builtin_amdgcn_readfirstlane(ro[y1]);
+            if (lo >= 0 && lo <= hi && (int64_t)hi <= la.capacity) {
+                walk_list<EXACT>(lo, hi, eat4, eat1);
+                return;
             }
-            for (; k < hi; ++k) {
-                float t, g, d;
-                uint32_t uv;
-                sample(rp + (int64_t)k * kRecWords, t, g, d, uv);
-                eat1(t, g, d, uv);
-            }
-            return;
         }
         // ---- stream the block's halo from the images ----
         const int hx0 = max(bx - r, 0), hx1 = min(bx + 8 + r, W);
