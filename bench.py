@@ -1,7 +1,9 @@
 """Benchmark: Full-HD LiDAR densification frames/s on one MI355X.
 
 Main line (``value``): one step = the whole hot path on one synthetic
-Full-HD viewpoint whose inputs are already resident in HBM: projection of
+Full-HD viewpoint whose inputs are already resident in HBM, launched
+eagerly (the rate of the same steps replayed as HIP graphs is printed
+beside it): projection of
 the ~2e5 merged points of three staggered 32-beam sweeps (clear + project +
 decode), the per-strip sample lists, and the r = 15, sigma_s = 6,
 sigma_r = 15 joint bilateral filter. Input and output buffers rotate over
@@ -462,16 +464,38 @@ def main():
     pairs = window_pairs(valid_np, r)
 
     # throughput: K steps back to back, no events between kernels (an event
-    # recorded between two kernels idles the GPU for a few microseconds)
+    # recorded between two kernels idles the GPU for a few microseconds);
+    # eager launches give the value; the same steps captured once per buffer
+    # set as HIP graphs and replayed are timed for comparison
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(sets[k % n_sets])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = wall * 1e3 / args.steps
-    fps = args.steps / wall
-    print(f"[bench] main: {fps:.1f} frames/s", flush=True)
+    eager_wall = time.perf_counter() - t0
+    graphs = []
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    for bset in sets:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+            step(bset)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    for k in range(min(args.warmup, n_sets)):
+        graphs[k % n_sets].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        graphs[k % n_sets].replay()
+    torch.cuda.synchronize()
+    graph_wall = time.perf_counter() - t0
+    step_ms = eager_wall * 1e3 / args.steps
+    fps = args.steps / eager_wall
+    graph_fps = args.steps / graph_wall
+    print(f"[bench] main: {fps:.1f} frames/s (eager), {graph_fps:.1f} as "
+          f"graph replays", flush=True)
+    del graphs
 
     # per-kernel durations: a second pass with HIP events recorded on the
     # launch stream around each stage
@@ -589,6 +613,7 @@ def main():
         "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(step_ms, 4), "higher_is_better": True,
+        "graph_replay_frames_per_s": round(graph_fps, 2),
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "fullhd_single_view", "width": W, "height": H,

@@ -198,14 +198,16 @@ def test_filter_random(torch_dev, case, path):
                  ws="auto" if path == "lists" else None)
 
 
-def test_filter_list_overflow_falls_back(torch_dev):
-    """A workspace sized for fewer samples than the image holds: the lists
-    are abandoned on the device and the filter streams the inputs."""
+@pytest.mark.parametrize("frac", [0.0, 0.05, 0.33, 0.9])
+def test_filter_list_overflow_falls_back(torch_dev, frac):
+    """A workspace sized for fewer samples than the image holds: blocks
+    whose list range does not fit stream their halo instead (strips early in
+    the list fit, later ones do not), with the same results."""
     torch, dev = torch_dev
     d, b, rgb = S.tiny_random(np.random.default_rng(9), 90, 120, 0.2,
                               n_colors=4)
     check_filter(torch, dev, d, b, rgb, 6, 3.0, 12.0, ws="auto",
-                 max_samples=int(b.sum()) // 3)
+                 max_samples=int(int(b.sum()) * frac))
 
 
 def test_filter_paths_agree(torch_dev):
@@ -284,3 +286,57 @@ def test_pipeline_scene(torch_dev, cfg):
           f"mean_rel={rel.mean():.3e}", flush=True)
     assert rel.max() <= REL_TOL
     assert np.all(out[~sel] == 0)
+
+
+def test_single_view_step_graph_replays(torch_dev):
+    """project + densify_prepare + densify captured once in a HIP graph and
+    replayed with new points and colours copied into the same buffers:
+    every replay equals the eager calls on the same inputs."""
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import (densify, densify_prepare,
+                                      densify_workspace, project)
+    frames = [S.small_view(np.random.default_rng(70 + k), 320, 240,
+                           n_points=6000) for k in range(3)]
+    cam = frames[0].camera
+    W, H, r = cam.width, cam.height, 5
+    pts = torch.empty((6000, 3), dtype=torch.float32, device=dev)
+    rgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
+    zb = torch.empty((H, W), dtype=torch.int64, device=dev)
+    d = torch.empty((H, W), dtype=torch.float32, device=dev)
+    v = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    m = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    ws = densify_workspace(H, W, r, 6000, dev)
+
+    def step():
+        project(pts, cam.pose, cam.intrinsics(), W, H, zbuf=zb, depth=d,
+                valid=v)
+        densify_prepare(d, v, rgb, r, ws)
+        densify(d, v, rgb, r, 3.0, 12.0, out=out, mask=m, ws=ws,
+                lists_ready=True)
+
+    pts.copy_(torch.from_numpy(frames[0].points))
+    rgb.copy_(torch.from_numpy(frames[0].rgb))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    for k in (1, 2, 0, 1):
+        f = frames[k]
+        pts.copy_(torch.from_numpy(f.points))
+        rgb.copy_(torch.from_numpy(f.rgb))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (out.clone(), m.clone(), zb.clone())
+        step()
+        torch.cuda.synchronize()
+        assert torch.equal(got[2], zb)
+        assert torch.equal(got[1], m)
+        assert torch.equal(got[0].view(torch.int32), out.view(torch.int32))
