@@ -14,6 +14,9 @@ Functions (the C file documents the formulas and the passages they follow):
 * :func:`densify_grad`    gradient w.r.t. depths, sigma_s, sigma_r
 * :func:`l1_holdout_loss` the self-supervised held-out L1 loss and its
                           upstream gradient
+* :func:`pool3`, :func:`restore_merge`, :func:`densify_two_stage`
+                          Sec. 5 two-stage filtering (pooled first pass,
+                          full-resolution second pass)
 """
 from __future__ import annotations
 
@@ -78,6 +81,12 @@ def lib():
                                           C.c_double, f64p, f64p,
                                           C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]
+        L.oracle_pool3.restype = None
+        L.oracle_pool3.argtypes = [f32p, u8p, u8p, C.c_int32, C.c_int32,
+                                   f32p, u8p, u8p]
+        L.oracle_restore_merge.restype = None
+        L.oracle_restore_merge.argtypes = [f32p, u8p, f32p, u8p, C.c_int32,
+                                           C.c_int32, f32p, u8p]
         L.oracle_num_threads.restype = C.c_int
         L.oracle_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -195,3 +204,46 @@ def l1_holdout_loss(outs, masks, targets, target_valid):
         loss += float(np.abs(diff).sum())
         grads.append(np.sign(diff) / n)
     return loss / n, grads
+
+
+def pool3(depth, valid, rgb):
+    """3x3 pooling (readings in oracle.c): (depth1 float32, valid1 uint8,
+    rgb1 uint8) at ((H+2)//3, (W+2)//3)."""
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    h1, w1 = (h + 2) // 3, (w + 2) // 3
+    d1 = np.empty((h1, w1), np.float32)
+    b1 = np.empty((h1, w1), np.uint8)
+    c1 = np.empty((h1, w1, 3), np.uint8)
+    lib().oracle_pool3(d, _c(valid, np.uint8), _c(rgb, np.uint8).reshape(h, w, 3),
+                       h, w, d1, b1, c1)
+    return d1, b1, c1
+
+
+def restore_merge(depth, valid, out1, mask1):
+    """Second-pass input: original depth where valid, else the first pass's
+    output of the pixel's cell where that is valid."""
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    d2 = np.empty((h, w), np.float32)
+    b2 = np.empty((h, w), np.uint8)
+    lib().oracle_restore_merge(d, _c(valid, np.uint8), _c(out1, np.float32),
+                               _c(mask1, np.uint8), h, w, d2, b2)
+    return d2, b2
+
+
+def densify_two_stage(depth, valid, rgb, r1, sigma_s1, sigma_r1, r2, sigma_s2,
+                      sigma_r2, want_stages: bool = False):
+    """Sec. 5 two-stage filter: pool3 -> densify (r1) -> restore_merge ->
+    densify (r2). The first pass's output is kept as float32 between the
+    stages (the precision of the stored depth map). Returns (out float64,
+    mask) and, with ``want_stages``, a dict of the intermediates."""
+    d1, b1, c1 = pool3(depth, valid, rgb)
+    o1, m1 = densify(d1, b1, c1, r1, sigma_s1, sigma_r1)
+    o1 = o1.astype(np.float32)
+    d2, b2 = restore_merge(depth, valid, o1, m1)
+    out, mask = densify(d2, b2, rgb, r2, sigma_s2, sigma_r2)
+    if want_stages:
+        return out, mask, dict(depth1=d1, valid1=b1, rgb1=c1, out1=o1,
+                               mask1=m1, depth2=d2, valid2=b2)
+    return out, mask

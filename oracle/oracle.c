@@ -441,3 +441,72 @@ void oracle_densify_grad(const float *depth, const uint8_t *valid,
     *grad_ss = gs;
     *grad_sr = gr;
 }
+
+/* ------------------------------------------------------------------------
+ * Two-stage filtering (Sec. 5: a first pass at one third of the resolution
+ * in each dimension, reached by pooling, then a pass at full resolution on
+ * the restored map). The paper names pooling and restoring without saying
+ * how; the readings here:
+ *   pooling   3x3 cells (the last row and column of cells may be partial:
+ *             they pool only the pixels inside the image); the pooled depth
+ *             is the mean of the cell's valid depths, summed in double in
+ *             row-major order and rounded once to float; the pooled mask
+ *             says whether the cell holds a valid depth; the pooled colour
+ *             is the rounded mean of every pixel of the cell per channel,
+ *             floor((sum + n/2) / n) in integers;
+ *   restoring nearest neighbour: full-resolution pixel (x, y) takes cell
+ *             (x / 3, y / 3) (integer division); the second pass sees the
+ *             original depth where B = 1, else the restored first-pass depth
+ *             where the first pass is valid, else nothing.
+ * ---------------------------------------------------------------------- */
+
+void oracle_pool3(const float *depth, const uint8_t *valid, const uint8_t *rgb,
+                  int32_t h, int32_t w, float *depth1, uint8_t *valid1,
+                  uint8_t *rgb1) {
+    const int32_t h1 = (h + 2) / 3, w1 = (w + 2) / 3;
+    for (int32_t cy = 0; cy < h1; ++cy) {
+        for (int32_t cx = 0; cx < w1; ++cx) {
+            double sum = 0.0;
+            int n_valid = 0, n_pix = 0;
+            int csum[3] = {0, 0, 0};
+            for (int32_t y = 3 * cy; y < 3 * cy + 3 && y < h; ++y) {
+                for (int32_t x = 3 * cx; x < 3 * cx + 3 && x < w; ++x) {
+                    const int64_t p = (int64_t)y * w + x;
+                    ++n_pix;
+                    for (int c = 0; c < 3; ++c) csum[c] += rgb[3 * p + c];
+                    if (valid[p]) {
+                        sum = sum + (double)depth[p];
+                        ++n_valid;
+                    }
+                }
+            }
+            const int64_t q = (int64_t)cy * w1 + cx;
+            depth1[q] = n_valid ? (float)(sum / (double)n_valid) : 0.0f;
+            valid1[q] = (uint8_t)(n_valid > 0);
+            for (int c = 0; c < 3; ++c)
+                rgb1[3 * q + c] = (uint8_t)((csum[c] + n_pix / 2) / n_pix);
+        }
+    }
+}
+
+void oracle_restore_merge(const float *depth, const uint8_t *valid,
+                          const float *out1, const uint8_t *mask1, int32_t h,
+                          int32_t w, float *depth2, uint8_t *valid2) {
+    const int32_t w1 = (w + 2) / 3;
+    for (int32_t y = 0; y < h; ++y) {
+        for (int32_t x = 0; x < w; ++x) {
+            const int64_t p = (int64_t)y * w + x;
+            const int64_t q = (int64_t)(y / 3) * w1 + x / 3;
+            if (valid[p]) {
+                depth2[p] = depth[p];
+                valid2[p] = 1;
+            } else if (mask1[q]) {
+                depth2[p] = out1[q];
+                valid2[p] = 1;
+            } else {
+                depth2[p] = 0.0f;
+                valid2[p] = 0;
+            }
+        }
+    }
+}

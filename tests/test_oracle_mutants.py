@@ -14,7 +14,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_SUITES = ["tests/test_oracle_project.py", "tests/test_oracle_filter.py",
-              "tests/test_oracle_grad.py"]
+              "tests/test_oracle_grad.py", "tests/test_oracle_two_stage.py"]
 
 # (name, text to replace, replacement, occurrences to replace or None = all)
 MUTANTS = [
@@ -38,6 +38,13 @@ MUTANTS = [
      "exp(-(c * kr) - (s * ks) - em);", 1),
     ("invalid_samples_in_sum", "                        if (!valid[q]) continue;\n                        const double c = (double)color_dist2(rgb, p, q);\n                        const double s = (double)(a * a + b * b);\n                        const double e = -(c * kr) - (s * ks);\n                        const double w = exp(e - em);",
      "                        const double c = (double)color_dist2(rgb, p, q);\n                        const double s = (double)(a * a + b * b);\n                        const double e = -(c * kr) - (s * ks);\n                        const double w = exp(e - em);", 1),
+    ("pool_divides_by_all_pixels", "(float)(sum / (double)n_valid)",
+     "(float)(sum / (double)n_pix)", 1),
+    ("pool_colour_truncates", "(csum[c] + n_pix / 2) / n_pix", "csum[c] / n_pix", 1),
+    ("restore_cell_rounded", "(int64_t)(y / 3) * w1 + x / 3",
+     "(int64_t)((y + 1) / 3) * w1 + x / 3", 1),
+    ("restore_prefers_first_pass", "            if (valid[p]) {\n                depth2[p] = depth[p];",
+     "            if (valid[p] && !mask1[q]) {\n                depth2[p] = depth[p];", 1),
 ]
 
 
