@@ -19,6 +19,9 @@ Further legs (``--legs``, all on by default):
   one graph-replayed batch vs the same views as single-view calls, FP32 and
   FP16 range weights;
 * ``fp16``     the Full-HD filter with FP16 range weights vs FP32;
+* ``two_stage`` the paper's two-stage configuration on the same Full-HD
+  frame: projection, 3x3 pooling, r = 4 pass at a third of the
+  resolution, restore, r = 2 pass at full resolution (dense kernel);
 * ``serving``  sixteen viewpoints (720p/1080p/4K, 50k-400k points, r = 5,
   FP16 range weights) with frames arriving on jittered 30 fps clocks:
   served (continuous batching) vs plain (one frame at a time), frames/s,
@@ -52,7 +55,10 @@ FLOPS_PER_PAIR = 14                 # per (output pixel, valid sample) pair
 ROTATE_BYTES = 600 << 20            # > 512 MB of distinct buffers
 FHD = 1920 * 1080
 LATENCY_TARGET_MS = 33.0
-LEGS = ("batched", "fp16", "serving", "fit")
+LEGS = ("batched", "fp16", "two_stage", "serving", "fit")
+# Sec. 5 and Table 1: the paper's own per-frame time for its two-stage
+# filter on Full-HD frames (context, another machine)
+PAPER_TWO_STAGE_MS = 23.0
 
 
 def parse():
@@ -259,6 +265,54 @@ def fp16_leg(torch, dev, b, r, ss, sr, steps):
     out["fp16_over_fp32"] = round(out["fp16_range_filter_ms"] /
                                   out["fp32_filter_ms"], 3)
     return out
+
+
+def two_stage_leg(torch, dev, sets, cam, steps):
+    from paper_2601_01210_amd import (densify_two_stage, project,
+                                      two_stage_ws_bytes)
+    W, H = cam.width, cam.height
+    params = (4, 2.0, 15.0, 2, 2.0, 15.0)
+    wss = [torch.empty(two_stage_ws_bytes(H, W), dtype=torch.uint8, device=dev)
+           for _ in sets]
+    stream = torch.cuda.current_stream(dev)
+
+    def step(k, ev=None):
+        b, ws = sets[k % len(sets)], wss[k % len(sets)]
+        if ev is not None:
+            ev[0].record(stream)
+        project(b["pts"], cam.pose, cam.intrinsics(), W, H, zbuf=b["zbuf"],
+                depth=b["d"], valid=b["v"])
+        if ev is not None:
+            ev[1].record(stream)
+        densify_two_stage(b["d"], b["v"], b["rgb"], *params, out=b["out"],
+                          mask=b["m"], ws=ws)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for k in range(10):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+           for _ in range(max(steps // 2, 10))]
+    for k, ev in enumerate(evs):
+        step(k, ev)
+    torch.cuda.synchronize()
+    valid = float(sets[0]["m"].float().mean())
+    return {"frames_per_s": round(steps / wall, 1),
+            "ms_per_frame": round(wall * 1e3 / steps, 4),
+            "project_ms": round(float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), 4),
+            "two_stage_ms": round(float(np.mean([e[1].elapsed_time(e[2]) for e in evs])), 4),
+            "radius1": params[0], "sigma_s1": params[1], "sigma_r1": params[2],
+            "radius2": params[3], "sigma_s2": params[4], "sigma_r2": params[5],
+            "valid_fraction_out": round(valid, 4),
+            "paper_ms_per_frame": PAPER_TWO_STAGE_MS,
+            "paper_context": "Sec. 5 / Table 1: two-stage filter on Full-HD "
+                             "frames, RTX 4090, PyTorch; another machine"}
 
 
 def serving_leg(torch, dev, frames, args):
@@ -574,6 +628,10 @@ def main():
         legs["fp16_fullhd"] = fp16_leg(torch, dev, sets[0], r, ss, sr,
                                        max(args.steps // 2, 10))
         print(f"[bench] fp16: {legs['fp16_fullhd']}", flush=True)
+    if "two_stage" in args.legs:
+        legs["two_stage_fullhd"] = two_stage_leg(torch, dev, sets, cam,
+                                                 max(args.steps // 2, 20))
+        print(f"[bench] two-stage: {legs['two_stage_fullhd']}", flush=True)
     del sets
     torch.cuda.synchronize()
     if "batched" in args.legs:

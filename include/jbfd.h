@@ -88,6 +88,13 @@ typedef enum jbfd_precision {
 #define JBFD_LISTS_READY 1u  /* ws already holds the sample lists of these
                                 inputs (from jbfd_densify_prepare): skip
                                 building them */
+#define JBFD_DENSE 2u        /* inputs where most pixels hold a sample: one
+                                thread per output pixel visits every tap of
+                                its window (radius <= JBFD_DENSE_MAX_RADIUS,
+                                FP32, no aux; ws is not used). Same weights
+                                as the sparse kernels; the sums may differ
+                                from theirs in the last bits (order). */
+#define JBFD_DENSE_MAX_RADIUS 4
 
 /* Pinhole intrinsics of a camera and the size of its image. */
 typedef struct jbfd_intrinsics {
@@ -286,6 +293,61 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
  * kernel variant and the LDS size). Capturable in a HIP graph. */
 jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
                            jbfd_precision prec, void *stream);
+
+/*
+ * Two-stage filtering (Sec. 5: a first pass at a third of the resolution
+ * in each dimension, reached by pooling, then a pass at full resolution on
+ * the restored map; radius 4 then 2 in the paper). The paper names pooling
+ * and restoring only; this library reads them as:
+ *
+ *   jbfd_pool3          3x3 cells; partial edge cells pool the pixels
+ *                       inside the image. Pooled depth = mean of the cell's
+ *                       valid depths (summed in double, row-major, rounded
+ *                       once to float), pooled valid = the cell holds a
+ *                       sample, pooled colour = floor((sum + n/2) / n) per
+ *                       channel over the cell's n pixels. Output size
+ *                       H1 = (H+2)/3, W1 = (W+2)/3.
+ *   jbfd_restore_merge  nearest restore: pixel (x, y) takes cell (x/3, y/3);
+ *                       the second pass sees the original depth where
+ *                       sparse_valid = 1, else the first pass's depth where
+ *                       its mask is 1, else nothing.
+ *   jbfd_densify_two_stage
+ *                       pool3 -> filter (radius1, sigmas1) at H1 x W1 ->
+ *                       restore_merge -> filter (radius2, sigmas2) at H x W.
+ *                       Each filter uses the dense kernel (JBFD_DENSE) when
+ *                       its radius is <= JBFD_DENSE_MAX_RADIUS, else the
+ *                       sparse kernel without lists. FP32.
+ *
+ * Buffers are device pointers; sizes and errors as jbfd_densify. The two-
+ * stage call keeps its intermediates in ws (device, 256-byte aligned, at
+ * least jbfd_two_stage_ws_bytes(H, W) bytes, else JBFD_ENOSPC).
+ */
+typedef struct jbfd_two_stage {
+    int32_t radius1;          /* first pass, at (H+2)/3 x (W+2)/3 */
+    float sigma_s1, sigma_r1; /* sigma_s1 in pooled pixels */
+    int32_t radius2;          /* second pass, at H x W */
+    float sigma_s2, sigma_r2;
+} jbfd_two_stage;
+
+jbfd_status jbfd_pool3(const float *sparse_depth, const uint8_t *sparse_valid,
+                       const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                       float *depth1, uint8_t *valid1, uint8_t *rgb1,
+                       void *stream);
+
+jbfd_status jbfd_restore_merge(const float *sparse_depth,
+                               const uint8_t *sparse_valid,
+                               const float *depth1, const uint8_t *valid1,
+                               int32_t H, int32_t W, float *depth2,
+                               uint8_t *valid2, void *stream);
+
+size_t jbfd_two_stage_ws_bytes(int32_t H, int32_t W);
+
+jbfd_status jbfd_densify_two_stage(const float *sparse_depth,
+                                   const uint8_t *sparse_valid,
+                                   const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                                   const jbfd_two_stage *params,
+                                   float *dense_depth, uint8_t *dense_valid,
+                                   void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -10,5 +10,6 @@ raise.
 from .binding import (BatchView, JbfdError, Precision,  # noqa: F401
                       abi_version, batch_run, batch_table_bytes,
                       batch_upload, densify, densify_backward,
-                      densify_prepare, densify_workspace, densify_ws_bytes,
-                      library_path, project)
+                      densify_prepare, densify_two_stage, densify_workspace,
+                      densify_ws_bytes, library_path, pool3, project,
+                      restore_merge, two_stage_ws_bytes)

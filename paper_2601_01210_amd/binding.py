@@ -38,6 +38,13 @@ class Intrinsics(C.Structure):
                 ("height", C.c_int32)]
 
 
+class TwoStage(C.Structure):
+    """Mirror of jbfd_two_stage (include/jbfd.h)."""
+    _fields_ = [("radius1", C.c_int32), ("sigma_s1", C.c_float),
+                ("sigma_r1", C.c_float), ("radius2", C.c_int32),
+                ("sigma_s2", C.c_float), ("sigma_r2", C.c_float)]
+
+
 class View(C.Structure):
     """Mirror of jbfd_view (include/jbfd.h)."""
     _fields_ = [("points", C.c_void_p), ("n_points", C.c_int64),
@@ -89,6 +96,16 @@ def lib():
                                             vp]
         L.jbfd_densify_backward_ws_bytes.restype = sz
         L.jbfd_densify_backward_ws_bytes.argtypes = [i32, i32]
+        L.jbfd_pool3.restype = C.c_int
+        L.jbfd_pool3.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.jbfd_restore_merge.restype = C.c_int
+        L.jbfd_restore_merge.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+        L.jbfd_two_stage_ws_bytes.restype = sz
+        L.jbfd_two_stage_ws_bytes.argtypes = [i32, i32]
+        L.jbfd_densify_two_stage.restype = C.c_int
+        L.jbfd_densify_two_stage.argtypes = [vp, vp, vp, i32, i32,
+                                             C.POINTER(TwoStage), vp, vp, vp,
+                                             sz, vp]
         L.jbfd_batch_table_bytes.restype = sz
         L.jbfd_batch_table_bytes.argtypes = [i32]
         L.jbfd_batch_prepare.restype = C.c_int
@@ -190,16 +207,22 @@ def densify_workspace(h: int, w: int, radius: int, max_samples: int,
     return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
 
 
+JBFD_LISTS_READY, JBFD_DENSE = 1, 2
+
+
 def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
             precision: Precision = Precision.FP32, out=None, mask=None,
             aux=None, want_aux: bool = False, ws="auto",
-            max_samples: Optional[int] = None, lists_ready: bool = False):
+            max_samples: Optional[int] = None, lists_ready: bool = False,
+            dense: bool = False):
     """Joint bilateral filter (jbfd_densify).
 
     depth (H,W) float32, valid (H,W) uint8, rgb (H,W,3) uint8, all on the
     device. ``ws`` is a workspace tensor from :func:`densify_workspace`,
     ``None`` (filter streams the inputs directly) or "auto" (allocate one
     sized for ``max_samples`` valid samples, default H*W/4).
+    ``dense`` selects the kernel for inputs where most pixels hold a
+    sample (radius <= 4, FP32, no aux; the workspace is not used).
     Returns (dense depth float32, mask uint8[, aux float32 (H,W,2)]).
     """
     torch = _torch()
@@ -220,6 +243,8 @@ def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
         aux = torch.empty((h, w, 2), dtype=torch.float32, device=dev)
     if aux is not None:
         _need(aux, torch.float32, (h, w, 2), "aux")
+    if dense:
+        ws = None
     if isinstance(ws, str):
         if ws != "auto":
             raise ValueError("ws must be a tensor, None or 'auto'")
@@ -232,7 +257,8 @@ def densify(depth, valid, rgb, radius: int, sigma_s: float, sigma_r: float,
                               int(precision), _ptr(out), _ptr(mask),
                               _ptr(aux), _ptr(ws),
                               ws.numel() if ws is not None else 0,
-                              1 if lists_ready else 0, _stream(dev)))
+                              (JBFD_LISTS_READY if lists_ready else 0) |
+                              (JBFD_DENSE if dense else 0), _stream(dev)))
     if aux is not None:
         return out, mask, aux
     return out, mask
@@ -405,3 +431,75 @@ def batch_run(table, max_radius: int, precision: Precision = Precision.FP32):
     _need(table, torch.uint8, None, "table")
     _check(lib().jbfd_batch_run(_ptr(table), int(max_radius), int(precision),
                                 _stream(table.device)))
+
+
+# ---------------------------------------------------------------------------
+# two-stage filtering (jbfd_pool3, jbfd_restore_merge, jbfd_densify_two_stage)
+# ---------------------------------------------------------------------------
+
+def pool3(depth, valid, rgb):
+    """3x3 pooling: (depth1 float32, valid1 uint8, rgb1 uint8) at
+    ((H+2)//3, (W+2)//3)."""
+    torch = _torch()
+    h, w = depth.shape
+    _need(depth, torch.float32, (h, w), "depth")
+    _need(valid, torch.uint8, (h, w), "valid")
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    h1, w1 = (h + 2) // 3, (w + 2) // 3
+    dev = depth.device
+    d1 = torch.empty((h1, w1), dtype=torch.float32, device=dev)
+    b1 = torch.empty((h1, w1), dtype=torch.uint8, device=dev)
+    c1 = torch.empty((h1, w1, 3), dtype=torch.uint8, device=dev)
+    _check(lib().jbfd_pool3(_ptr(depth), _ptr(valid), _ptr(rgb), h, w, _ptr(d1),
+                            _ptr(b1), _ptr(c1), _stream(dev)))
+    return d1, b1, c1
+
+
+def restore_merge(depth, valid, out1, mask1):
+    """Second-pass input: the original depth where valid, else the first
+    pass's output of the pixel's 3x3 cell where that is valid."""
+    torch = _torch()
+    h, w = depth.shape
+    h1, w1 = (h + 2) // 3, (w + 2) // 3
+    _need(depth, torch.float32, (h, w), "depth")
+    _need(valid, torch.uint8, (h, w), "valid")
+    _need(out1, torch.float32, (h1, w1), "out1")
+    _need(mask1, torch.uint8, (h1, w1), "mask1")
+    dev = depth.device
+    d2 = torch.empty((h, w), dtype=torch.float32, device=dev)
+    b2 = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    _check(lib().jbfd_restore_merge(_ptr(depth), _ptr(valid), _ptr(out1),
+                                    _ptr(mask1), h, w, _ptr(d2), _ptr(b2),
+                                    _stream(dev)))
+    return d2, b2
+
+
+def two_stage_ws_bytes(h: int, w: int) -> int:
+    return int(lib().jbfd_two_stage_ws_bytes(h, w))
+
+
+def densify_two_stage(depth, valid, rgb, radius1: int, sigma_s1: float,
+                      sigma_r1: float, radius2: int, sigma_s2: float,
+                      sigma_r2: float, out=None, mask=None, ws=None):
+    """Two-stage filter (jbfd_densify_two_stage): returns (dense depth,
+    mask); ``ws`` (device uint8, two_stage_ws_bytes) is allocated if None."""
+    torch = _torch()
+    h, w = depth.shape
+    _need(depth, torch.float32, (h, w), "depth")
+    _need(valid, torch.uint8, (h, w), "valid")
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    dev = depth.device
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if mask is None:
+        mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    if ws is None:
+        ws = torch.empty(max(two_stage_ws_bytes(h, w), 256), dtype=torch.uint8,
+                         device=dev)
+    _need(ws, torch.uint8, None, "ws")
+    p = TwoStage(int(radius1), float(sigma_s1), float(sigma_r1), int(radius2),
+                 float(sigma_s2), float(sigma_r2))
+    _check(lib().jbfd_densify_two_stage(_ptr(depth), _ptr(valid), _ptr(rgb), h, w,
+                                        C.byref(p), _ptr(out), _ptr(mask),
+                                        _ptr(ws), ws.numel(), _stream(dev)))
+    return out, mask

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjbfd.so")
-SOURCES = ["api.hip", "project.hip", "densify.hip", "backward.hip"]
+SOURCES = ["api.hip", "project.hip", "densify.hip", "backward.hip",
+           "stage2.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

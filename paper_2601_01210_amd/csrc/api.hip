@@ -136,10 +136,21 @@ jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,
     if (ws && ((uintptr_t)ws & 255))
         return fail(JBFD_EINVAL, "jbfd_densify: workspace not 256-byte aligned");
     if (!ws) ws_bytes = 0;
-    if (flags & ~JBFD_LISTS_READY)
+    if (flags & ~(JBFD_LISTS_READY | JBFD_DENSE))
         return fail(JBFD_EINVAL, "jbfd_densify: unknown flags 0x%x", flags);
     jbfd::FilterParams fp{radius, log2_half_inv_var(sigma_r),
                           log2_half_inv_var(sigma_s)};
+    if (flags & JBFD_DENSE) {
+        if (radius > JBFD_DENSE_MAX_RADIUS || prec != JBFD_FP32 || aux)
+            return fail(JBFD_EUNSUPPORTED,
+                        "jbfd_densify: the dense kernel takes radius <= %d, "
+                        "FP32 and no aux", JBFD_DENSE_MAX_RADIUS);
+        return hip_status(jbfd::launch_densify_dense(sparse_depth, sparse_valid,
+                                                     rgb_hwc, H, W, fp,
+                                                     dense_depth, dense_valid,
+                                                     (hipStream_t)stream),
+                          "jbfd_densify");
+    }
     hipError_t e = jbfd::launch_densify(sparse_depth, sparse_valid, rgb_hwc, H, W,
                                         fp, prec, dense_depth, dense_valid, aux,
                                         ws, ws_bytes, (flags & JBFD_LISTS_READY) != 0,
@@ -207,6 +218,69 @@ size_t jbfd_densify_ws_bytes(int32_t H, int32_t W, int32_t radius,
 size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W) {
     if (H <= 0 || W <= 0) return 0;
     return jbfd::backward_ws_bytes(H, W);
+}
+
+jbfd_status jbfd_pool3(const float *sparse_depth, const uint8_t *sparse_valid,
+                       const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                       float *depth1, uint8_t *valid1, uint8_t *rgb1,
+                       void *stream) {
+    if (!sparse_depth || !sparse_valid || !rgb_hwc || !depth1 || !valid1 || !rgb1)
+        return fail(JBFD_EINVAL, "jbfd_pool3: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    return hip_status(jbfd::launch_pool3(sparse_depth, sparse_valid, rgb_hwc, H, W,
+                                         depth1, valid1, rgb1, (hipStream_t)stream),
+                      "jbfd_pool3");
+}
+
+jbfd_status jbfd_restore_merge(const float *sparse_depth,
+                               const uint8_t *sparse_valid,
+                               const float *depth1, const uint8_t *valid1,
+                               int32_t H, int32_t W, float *depth2,
+                               uint8_t *valid2, void *stream) {
+    if (!sparse_depth || !sparse_valid || !depth1 || !valid1 || !depth2 || !valid2)
+        return fail(JBFD_EINVAL, "jbfd_restore_merge: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    return hip_status(jbfd::launch_restore_merge(sparse_depth, sparse_valid, depth1,
+                                                 valid1, H, W, depth2, valid2,
+                                                 (hipStream_t)stream),
+                      "jbfd_restore_merge");
+}
+
+size_t jbfd_two_stage_ws_bytes(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE) return 0;
+    return jbfd::two_stage_ws_bytes(H, W);
+}
+
+jbfd_status jbfd_densify_two_stage(const float *sparse_depth,
+                                   const uint8_t *sparse_valid,
+                                   const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                                   const jbfd_two_stage *params,
+                                   float *dense_depth, uint8_t *dense_valid,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    if (!sparse_depth || !sparse_valid || !rgb_hwc || !params || !dense_depth ||
+        !dense_valid || !ws)
+        return fail(JBFD_EINVAL, "jbfd_densify_two_stage: null buffer or params");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    st = check_filter(params->radius1, params->sigma_s1, params->sigma_r1);
+    if (st != JBFD_OK) return st;
+    st = check_filter(params->radius2, params->sigma_s2, params->sigma_r2);
+    if (st != JBFD_OK) return st;
+    if ((uintptr_t)ws & 255)
+        return fail(JBFD_EINVAL, "jbfd_densify_two_stage: workspace not aligned");
+    if (ws_bytes < jbfd::two_stage_ws_bytes(H, W))
+        return fail(JBFD_ENOSPC, "jbfd_densify_two_stage: workspace %zu < %zu bytes",
+                    ws_bytes, jbfd::two_stage_ws_bytes(H, W));
+    const jbfd::FilterParams f1{params->radius1, log2_half_inv_var(params->sigma_r1),
+                                log2_half_inv_var(params->sigma_s1)};
+    const jbfd::FilterParams f2{params->radius2, log2_half_inv_var(params->sigma_r2),
+                                log2_half_inv_var(params->sigma_s2)};
+    return hip_status(jbfd::launch_two_stage(sparse_depth, sparse_valid, rgb_hwc, H,
+                                             W, f1, f2, dense_depth, dense_valid,
+                                             ws, (hipStream_t)stream),
+                      "jbfd_densify_two_stage");
 }
 
 size_t jbfd_batch_table_bytes(int32_t n_views) {

@@ -105,6 +105,25 @@ __device__ inline int batch_view_of(const BatchView *views, int n_views, int c) 
     return lo;
 }
 
+// Two-stage filtering and the dense small-radius filter (stage2.hip).
+constexpr int kDenseMaxRadius = JBFD_DENSE_MAX_RADIUS;
+hipError_t launch_pool3(const float *D, const uint8_t *B, const uint8_t *rgb,
+                        int32_t H, int32_t W, float *D1, uint8_t *B1,
+                        uint8_t *rgb1, hipStream_t s);
+hipError_t launch_restore_merge(const float *D, const uint8_t *B,
+                                const float *O1, const uint8_t *M1, int32_t H,
+                                int32_t W, float *D2, uint8_t *B2,
+                                hipStream_t s);
+hipError_t launch_densify_dense(const float *D, const uint8_t *B,
+                                const uint8_t *rgb, int32_t H, int32_t W,
+                                const FilterParams &fp, float *out,
+                                uint8_t *mask, hipStream_t s);
+size_t two_stage_ws_bytes(int32_t H, int32_t W);
+hipError_t launch_two_stage(const float *D, const uint8_t *B, const uint8_t *rgb,
+                            int32_t H, int32_t W, const FilterParams &f1,
+                            const FilterParams &f2, float *out, uint8_t *mask,
+                            void *ws, hipStream_t s);
+
 hipError_t launch_batch(const void *d_table, int32_t max_radius,
                         jbfd_precision prec, hipStream_t s);
 hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,

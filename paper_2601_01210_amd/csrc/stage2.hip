@@ -1,0 +1,279 @@
+// Two-stage filtering (Sec. 5): the sparse depth image is pooled to a third
+// of its resolution in each dimension, filtered there, restored to full
+// resolution and filtered again with a small radius.
+//
+//   k_pool3          one thread per 3x3 cell: valid-average depth (summed in
+//                    double in row-major order, rounded once to float), cell
+//                    validity, rounded mean colour floor((sum + n/2) / n);
+//   k_restore_merge  four pixels per thread: the original depth where the
+//                    pixel holds a sample, else the first pass's output of
+//                    its cell (x/3, y/3) where that is valid;
+//   k_jbf_dense<R>   the joint bilateral filter (Eq. 1-4) for inputs where
+//                    most pixels hold a sample and the radius is small: one
+//                    thread per output pixel loops over every tap of its
+//                    (2R+1)^2 window, read from a 16x16 tile plus halo staged
+//                    in LDS. After pooling and restoring, nearly every window
+//                    tap is valid, so a wave-uniform walk over sample lists
+//                    (the sparse kernel) would spend most of its lanes
+//                    outside the small windows.
+//
+// Weights of k_jbf_dense follow the sparse kernel's pass 1 exactly (same
+// exponent form and clamps: colour part max(2 kr t - kr|p|^2, -60) with
+// t = p.q - |q|^2/2 from f16 channel values, spatial part
+// max(-ks (dx^2+dy^2), -60)), so every in-window sample has a weight of at
+// least 2^-120 and den > 0 is exactly the mask; lanes whose weight sum ends
+// below 2^-16 are recomputed with the exact running shift of the sparse
+// kernel's pass 2. A tile record is {(r,g) f16x2, (b, valid) f16x2, depth,
+// -|q|^2/2}; the valid flag in the upper half of the second word multiplies
+// the weight into den through one mixed-precision fma, and invalid pixels
+// carry depth 0, so they add nothing to either sum.
+#include "filter_common.hpp"
+
+namespace jbfd {
+
+__global__ __launch_bounds__(256) void k_pool3(const float *__restrict__ D,
+                                               const uint8_t *__restrict__ B,
+                                               const uint8_t *__restrict__ rgb,
+                                               int H, int W,
+                                               float *__restrict__ D1,
+                                               uint8_t *__restrict__ B1,
+                                               uint8_t *__restrict__ rgb1) {
+    const int H1 = (H + 2) / 3, W1 = (W + 2) / 3;
+    const int64_t n = (int64_t)H1 * W1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += stride) {
+        const int cy = (int)(q / W1), cx = (int)(q - (int64_t)cy * W1);
+        double sum = 0.0;
+        int n_valid = 0, n_pix = 0;
+        int c0 = 0, c1 = 0, c2 = 0;
+        for (int y = 3 * cy; y < 3 * cy + 3 && y < H; ++y) {
+            for (int x = 3 * cx; x < 3 * cx + 3 && x < W; ++x) {
+                const int64_t p = (int64_t)y * W + x;
+                ++n_pix;
+                c0 += rgb[3 * p];
+                c1 += rgb[3 * p + 1];
+                c2 += rgb[3 * p + 2];
+                if (B[p]) {
+                    sum = sum + (double)D[p];
+                    ++n_valid;
+                }
+            }
+        }
+        D1[q] = n_valid ? (float)(sum / (double)n_valid) : 0.0f;
+        B1[q] = (uint8_t)(n_valid > 0);
+        rgb1[3 * q] = (uint8_t)((c0 + n_pix / 2) / n_pix);
+        rgb1[3 * q + 1] = (uint8_t)((c1 + n_pix / 2) / n_pix);
+        rgb1[3 * q + 2] = (uint8_t)((c2 + n_pix / 2) / n_pix);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_restore_merge(
+    const float *__restrict__ D, const uint8_t *__restrict__ B,
+    const float *__restrict__ O1, const uint8_t *__restrict__ M1, int H, int W,
+    float *__restrict__ D2, uint8_t *__restrict__ B2) {
+    const int W1 = (W + 2) / 3;
+    const int64_t n = (int64_t)H * W;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += stride) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const int64_t q = (int64_t)(y / 3) * W1 + x / 3;
+        const bool own = B[p] != 0;
+        const bool up = M1[q] != 0;
+        D2[p] = own ? D[p] : (up ? O1[q] : 0.0f);
+        B2[p] = (uint8_t)(own || up);
+    }
+}
+
+// Filter of one 16x16 tile with one thread per pixel (see the file comment).
+template <int R>
+__global__ __launch_bounds__(256) void k_jbf_dense(
+    const float *__restrict__ D, const uint8_t *__restrict__ B,
+    const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
+    int tiles_x, int n_tiles, int n_pad, float *__restrict__ out,
+    uint8_t *__restrict__ mask) {
+    constexpr int E = kTile + 2 * R;          // tile edge with halo
+    __shared__ uint4 tile[E * E];
+    const int t = xcd_tile(blockIdx.x, n_pad);
+    if (t >= n_tiles) return;                 // whole workgroup leaves together
+    const int ty0 = (t / tiles_x) * kTile, tx0 = (t % tiles_x) * kTile;
+
+    // stage the tile and its halo: invalid and out-of-image pixels get a
+    // zero depth and a zero valid flag
+    for (int e = threadIdx.x; e < E * E; e += 256) {
+        const int ly = e / E, lx = e - ly * E;
+        const int y = ty0 - R + ly, x = tx0 - R + lx;
+        uint4 rec = make_uint4(0u, 0u, 0u, 0u);
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            const int64_t p = (int64_t)y * W + x;
+            const uint8_t *c = rgb + 3 * p;
+            uint32_t rg, b0;
+            float nq2h;
+            colour_fields((uint32_t)c[0] | ((uint32_t)c[1] << 8), c[2], rg, b0, nq2h);
+            const bool v = B[p] != 0;
+            // valid flag = f16 1.0 in the upper half of the (b, 0) word
+            rec = make_uint4(rg, b0 | (v ? 0x3C000000u : 0u),
+                             __float_as_uint(v ? D[p] : 0.0f), __float_as_uint(nq2h));
+        }
+        tile[e] = rec;
+    }
+    __syncthreads();
+
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int px = tx0 + lx, py = ty0 + ly;
+    if (px >= W || py >= H) return;           // no barrier follows
+    const uint4 me = tile[(ly + R) * E + lx + R];
+    const uint32_t prg = me.x, pb0 = me.y & 0xFFFFu;   // (b, 0) for the dot
+    const float p2 = -2.0f * __uint_as_float(me.w);
+    const float kr2 = 2.0f * fp.kr;
+    const float Mfast = -fp.kr * p2;
+
+    // spatial exponents of the distinct squared distances, clamped as in
+    // the sparse kernel's table
+    float gs[2 * R * R + 1];
+#pragma unroll
+    for (int s = 0; s <= 2 * R * R; ++s)
+        gs[s] = fmaxf(-fp.ks * (float)s, kClampExp);
+
+    float num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            const uint4 q = tile[(ly + R + dy) * E + lx + R + dx];
+            const float tq = dot2h(prg, q.x, dot2h(pb0, q.y, __uint_as_float(q.w)));
+            const float a = fmaxf(__builtin_fmaf(kr2, tq, Mfast), kClampExp) +
+                            gs[dx * dx + dy * dy];
+            const float w = __builtin_amdgcn_exp2f(a);
+            const _Float16 vf = __builtin_bit_cast(h2, q.y)[1];
+            num = __builtin_fmaf(w, __uint_as_float(q.z), num);
+            den = __builtin_fmaf(w, (float)vf, den);
+        }
+    }
+
+    // exact pass for lanes whose weights are all tiny (far colours or tiny
+    // sigma_s): running shift, exact unclamped spatial exponents
+    if (den > 0.0f && den < kWeakBelow) {
+        float M = kShiftInit - fp.kr * p2, n2 = 0.0f, d2 = 0.0f;
+        for (int dy = -R; dy <= R; ++dy) {
+            for (int dx = -R; dx <= R; ++dx) {
+                const uint4 q = tile[(ly + R + dy) * E + lx + R + dx];
+                if ((q.y >> 16) == 0u) continue;
+                const float tq = dot2h(prg, q.x, dot2h(pb0, q.y, __uint_as_float(q.w)));
+                consume1(tq, -fp.ks * (float)(dx * dx + dy * dy),
+                         __uint_as_float(q.z), kr2, M, n2, d2);
+            }
+        }
+        num = n2;
+        den = d2;
+    }
+    const int64_t p = (int64_t)py * W + px;
+    const bool ok = den > 0.0f;
+    out[p] = ok ? num / den : 0.0f;
+    mask[p] = (uint8_t)ok;
+}
+
+static int blocks_for(int64_t work, int per_block) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (int)b;
+}
+
+hipError_t launch_pool3(const float *D, const uint8_t *B, const uint8_t *rgb,
+                        int32_t H, int32_t W, float *D1, uint8_t *B1,
+                        uint8_t *rgb1, hipStream_t s) {
+    const int64_t cells = (int64_t)((H + 2) / 3) * ((W + 2) / 3);
+    k_pool3<<<blocks_for(cells, 256), 256, 0, s>>>(D, B, rgb, H, W, D1, B1, rgb1);
+    return hipGetLastError();
+}
+
+hipError_t launch_restore_merge(const float *D, const uint8_t *B,
+                                const float *O1, const uint8_t *M1, int32_t H,
+                                int32_t W, float *D2, uint8_t *B2,
+                                hipStream_t s) {
+    k_restore_merge<<<blocks_for((int64_t)H * W, 256), 256, 0, s>>>(D, B, O1, M1,
+                                                                   H, W, D2, B2);
+    return hipGetLastError();
+}
+
+hipError_t launch_densify_dense(const float *D, const uint8_t *B,
+                                const uint8_t *rgb, int32_t H, int32_t W,
+                                const FilterParams &fp, float *out,
+                                uint8_t *mask, hipStream_t s) {
+    const int tiles_x = (W + kTile - 1) / kTile;
+    const int tiles_y = (H + kTile - 1) / kTile;
+    const int n_tiles = tiles_x * tiles_y;
+    const int n_pad = (n_tiles + 7) & ~7;
+    switch (fp.radius) {
+    case 0: k_jbf_dense<0><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
+    case 1: k_jbf_dense<1><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
+    case 2: k_jbf_dense<2><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
+    case 3: k_jbf_dense<3><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
+    case 4: k_jbf_dense<4><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Intermediates of the two-stage filter inside the caller's workspace.
+struct TwoStageLayout {
+    size_t d1, b1, c1, o1, m1, d2, b2, total;
+};
+
+static TwoStageLayout two_stage_layout(int32_t H, int32_t W) {
+    const size_t n1 = (size_t)((H + 2) / 3) * ((W + 2) / 3);
+    const size_t n = (size_t)H * W;
+    TwoStageLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    L.d1 = take(4 * n1);
+    L.b1 = take(n1);
+    L.c1 = take(3 * n1);
+    L.o1 = take(4 * n1);
+    L.m1 = take(n1);
+    L.d2 = take(4 * n);
+    L.b2 = take(n);
+    L.total = off;
+    return L;
+}
+
+size_t two_stage_ws_bytes(int32_t H, int32_t W) {
+    return two_stage_layout(H, W).total;
+}
+
+hipError_t launch_two_stage(const float *D, const uint8_t *B, const uint8_t *rgb,
+                            int32_t H, int32_t W, const FilterParams &f1,
+                            const FilterParams &f2, float *out, uint8_t *mask,
+                            void *ws, hipStream_t s) {
+    const TwoStageLayout L = two_stage_layout(H, W);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    float *D1 = reinterpret_cast<float *>(w + L.d1);
+    uint8_t *B1 = w + L.b1;
+    uint8_t *C1 = w + L.c1;
+    float *O1 = reinterpret_cast<float *>(w + L.o1);
+    uint8_t *M1 = w + L.m1;
+    float *D2 = reinterpret_cast<float *>(w + L.d2);
+    uint8_t *B2 = w + L.b2;
+    const int32_t H1 = (H + 2) / 3, W1 = (W + 2) / 3;
+    hipError_t e = launch_pool3(D, B, rgb, H, W, D1, B1, C1, s);
+    if (e != hipSuccess) return e;
+    e = f1.radius <= kDenseMaxRadius
+            ? launch_densify_dense(D1, B1, C1, H1, W1, f1, O1, M1, s)
+            : launch_densify(D1, B1, C1, H1, W1, f1, JBFD_FP32, O1, M1, nullptr,
+                             nullptr, 0, false, s);
+    if (e != hipSuccess) return e;
+    e = launch_restore_merge(D, B, O1, M1, H, W, D2, B2, s);
+    if (e != hipSuccess) return e;
+    return f2.radius <= kDenseMaxRadius
+               ? launch_densify_dense(D2, B2, rgb, H, W, f2, out, mask, s)
+               : launch_densify(D2, B2, rgb, H, W, f2, JBFD_FP32, out, mask,
+                                nullptr, nullptr, 0, false, s);
+}
+
+}  // namespace jbfd

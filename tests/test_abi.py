@@ -216,3 +216,35 @@ def test_batch_run_rejects_bad_arguments(L):
     assert L.jbfd_batch_run(fake, 33, 0, None) == JBFD_EINVAL
     assert L.jbfd_batch_run(fake, -1, 0, None) == JBFD_EINVAL
     assert L.jbfd_batch_run(fake, 5, 7, None) == JBFD_EINVAL
+
+
+def test_two_stage_and_dense_reject_bad_arguments(L):
+    from paper_2601_01210_amd.binding import (JBFD_EINVAL, JBFD_ENOSPC,
+                                              JBFD_EUNSUPPORTED, TwoStage)
+    fake = C.c_void_p(0x1000)
+    ws = C.c_void_p(0x10000)
+    assert L.jbfd_pool3(None, fake, fake, 8, 8, fake, fake, fake, None) == JBFD_EINVAL
+    assert L.jbfd_pool3(fake, fake, fake, 0, 8, fake, fake, fake, None) == JBFD_EINVAL
+    assert L.jbfd_restore_merge(fake, fake, fake, None, 8, 8, fake, fake,
+                                None) == JBFD_EINVAL
+    n = L.jbfd_two_stage_ws_bytes(1080, 1920)
+    assert n >= 1080 * 1920 * 5 + 360 * 640 * 13
+    assert L.jbfd_two_stage_ws_bytes(0, 5) == 0
+    p = TwoStage(4, 2.0, 15.0, 2, 2.0, 15.0)
+    args = lambda ws_, nb, pp: (fake, fake, fake, 1080, 1920, pp, fake, fake,
+                                ws_, nb, None)
+    assert L.jbfd_densify_two_stage(*args(ws, n - 1, C.byref(p))) == JBFD_ENOSPC
+    assert L.jbfd_densify_two_stage(*args(C.c_void_p(0x10010), n,
+                                          C.byref(p))) == JBFD_EINVAL
+    assert L.jbfd_densify_two_stage(*args(ws, n, None)) == JBFD_EINVAL
+    bad = TwoStage(4, 2.0, 15.0, 40, 2.0, 15.0)
+    assert L.jbfd_densify_two_stage(*args(ws, n, C.byref(bad))) == JBFD_EINVAL
+    bad = TwoStage(4, 0.1, 15.0, 2, 2.0, 15.0)
+    assert L.jbfd_densify_two_stage(*args(ws, n, C.byref(bad))) == JBFD_EINVAL
+    # dense kernel: radius <= 4, FP32, no aux
+    dargs = lambda r, prec, aux: (fake, fake, fake, 8, 8, r, 2.0, 10.0, prec,
+                                  fake, fake, aux, None, 0, 2, None)
+    assert L.jbfd_densify(*dargs(5, 0, None)) == JBFD_EUNSUPPORTED
+    assert L.jbfd_densify(*dargs(2, 1, None)) == JBFD_EUNSUPPORTED
+    assert L.jbfd_densify(*dargs(2, 0, fake)) == JBFD_EUNSUPPORTED
+    assert L.jbfd_densify(*dargs(2, 0, None)[:-2], 4, None) == JBFD_EINVAL
