@@ -17,6 +17,8 @@ Functions (the C file documents the formulas and the passages they follow):
 * :func:`pool3`, :func:`restore_merge`, :func:`densify_two_stage`
                           Sec. 5 two-stage filtering (pooled first pass,
                           full-resolution second pass)
+* :func:`remove_occluded` Sec. 4.1 occluded-point removal
+* :func:`backproject`     Sec. 5 contour removal + Sec. 2 coloured cloud
 """
 from __future__ import annotations
 
@@ -87,6 +89,12 @@ def lib():
         L.oracle_restore_merge.restype = None
         L.oracle_restore_merge.argtypes = [f32p, u8p, f32p, u8p, C.c_int32,
                                            C.c_int32, f32p, u8p]
+        L.oracle_remove_occluded.restype = None
+        L.oracle_remove_occluded.argtypes = [f32p, u8p, C.c_int32, C.c_int32,
+                                             C.c_int32, C.c_double, u8p]
+        L.oracle_backproject.restype = C.c_int64
+        L.oracle_backproject.argtypes = [f32p, u8p, u8p, C.c_int32, C.c_int32,
+                                         f64p, f64p, C.c_double, f32p, u8p]
         L.oracle_num_threads.restype = C.c_int
         L.oracle_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -247,3 +255,28 @@ def densify_two_stage(depth, valid, rgb, r1, sigma_s1, sigma_r1, r2, sigma_s2,
         return out, mask, dict(depth1=d1, valid1=b1, rgb1=c1, out1=o1,
                                mask1=m1, depth2=d2, valid2=b2)
     return out, mask
+
+
+def remove_occluded(depth, valid, k: int, tau: float):
+    """Valid mask with occluded samples dropped (readings in oracle.c)."""
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    out = np.empty((h, w), np.uint8)
+    lib().oracle_remove_occluded(d, _c(valid, np.uint8), h, w, int(k),
+                                 float(tau), out)
+    return out
+
+
+def backproject(dense, mask, rgb, pose, intrinsics, tau: float):
+    """Coloured world points of the kept output pixels, row-major:
+    (xyz float32 (n,3), rgb uint8 (n,3))."""
+    d = _c(dense, np.float32)
+    h, w = d.shape
+    xyz = np.empty((h * w, 3), np.float32)
+    col = np.empty((h * w, 3), np.uint8)
+    n = lib().oracle_backproject(d, _c(mask, np.uint8),
+                                 _c(rgb, np.uint8).reshape(h, w, 3), h, w,
+                                 _c(pose, np.float64).reshape(12),
+                                 _c(intrinsics[:4], np.float64), float(tau),
+                                 xyz, col)
+    return xyz[:n].copy(), col[:n].copy()

@@ -510,3 +510,99 @@ void oracle_restore_merge(const float *depth, const uint8_t *valid,
         }
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Occluded-point removal (Sec. 4.1: the merged depth map is averaged and
+ * points lying well behind the average are dropped as hidden from the
+ * camera). Readings: the average at a valid pixel is the mean of the valid
+ * depths in its (2k+1)^2 window (centre included, clipped at the border),
+ * summed in double in row-major order; the pixel's sample is dropped when
+ * D - mean > tau * mean, evaluated in double. One pass over the original
+ * map.
+ * ---------------------------------------------------------------------- */
+
+void oracle_remove_occluded(const float *depth, const uint8_t *valid, int32_t h,
+                            int32_t w, int32_t k, double tau, uint8_t *valid_out) {
+    for (int32_t y = 0; y < h; ++y) {
+        for (int32_t x = 0; x < w; ++x) {
+            const int64_t p = (int64_t)y * w + x;
+            if (!valid[p]) {
+                valid_out[p] = 0;
+                continue;
+            }
+            double sum = 0.0;
+            int n = 0;
+            for (int32_t yy = y - k; yy <= y + k; ++yy) {
+                if (yy < 0 || yy >= h) continue;
+                for (int32_t xx = x - k; xx <= x + k; ++xx) {
+                    if (xx < 0 || xx >= w) continue;
+                    const int64_t q = (int64_t)yy * w + xx;
+                    if (valid[q]) {
+                        sum = sum + (double)depth[q];
+                        ++n;
+                    }
+                }
+            }
+            const double mean = sum / (double)n;
+            valid_out[p] = (uint8_t)!((double)depth[p] - mean > tau * mean);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Contour removal and back-projection to a coloured point cloud (Sec. 5:
+ * unreliable depths along object contours are removed by thresholding the
+ * depth gradient; Sec. 2: each viewpoint's coloured points are placed in
+ * the common world frame). Readings: the gradient at a valid output pixel
+ * is the largest |D(n) - D(x)| over its valid 4-neighbours (0 if it has
+ * none), in double; the pixel is removed when that exceeds tau * D(x). A
+ * kept pixel (col, row) becomes the camera point ((col + 0.5 - cx) Z / fx,
+ * (row + 0.5 - cy) Z / fy, Z), Z = D(x), then the world point
+ * R^T (p_c - t) for the camera-from-world pose [R|t], each coordinate a
+ * left-to-right sum in double without FMA, rounded once to float. Points
+ * are written in row-major pixel order with the pixel's colour.
+ * ---------------------------------------------------------------------- */
+
+static int contour_keep(const float *d, const uint8_t *m, int32_t h, int32_t w,
+                        int32_t x, int32_t y, double tau) {
+    const int64_t p = (int64_t)y * w + x;
+    const double z = (double)d[p];
+    double g = 0.0;
+    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+    for (int i = 0; i < 4; ++i) {
+        const int32_t xx = x + dx[i], yy = y + dy[i];
+        if (xx < 0 || xx >= w || yy < 0 || yy >= h) continue;
+        const int64_t q = (int64_t)yy * w + xx;
+        if (!m[q]) continue;
+        const double diff = fabs((double)d[q] - z);
+        if (diff > g) g = diff;
+    }
+    return !(g > tau * z);
+}
+
+int64_t oracle_backproject(const float *dense, const uint8_t *mask,
+                           const uint8_t *rgb, int32_t h, int32_t w,
+                           const double *pose, const double *K, double tau,
+                           float *xyz, uint8_t *rgb_out) {
+    const double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
+    int64_t n = 0;
+    for (int32_t y = 0; y < h; ++y) {
+        for (int32_t x = 0; x < w; ++x) {
+            const int64_t p = (int64_t)y * w + x;
+            if (!mask[p] || !contour_keep(dense, mask, h, w, x, y, tau)) continue;
+            const double Z = (double)dense[p];
+            const double Xc = ((double)x + 0.5 - cx) * Z / fx;
+            const double Yc = ((double)y + 0.5 - cy) * Z / fy;
+            const double a = Xc - pose[3], b = Yc - pose[7], c = Z - pose[11];
+            for (int i = 0; i < 3; ++i) {
+                double s = pose[0 + i] * a;
+                s = s + pose[4 + i] * b;
+                s = s + pose[8 + i] * c;
+                xyz[3 * n + i] = (float)s;
+            }
+            for (int i = 0; i < 3; ++i) rgb_out[3 * n + i] = rgb[3 * p + i];
+            ++n;
+        }
+    }
+    return n;
+}

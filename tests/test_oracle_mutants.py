@@ -14,7 +14,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_SUITES = ["tests/test_oracle_project.py", "tests/test_oracle_filter.py",
-              "tests/test_oracle_grad.py", "tests/test_oracle_two_stage.py"]
+              "tests/test_oracle_grad.py", "tests/test_oracle_two_stage.py",
+              "tests/test_oracle_cloud.py"]
 
 # (name, text to replace, replacement, occurrences to replace or None = all)
 MUTANTS = [
@@ -43,6 +44,14 @@ MUTANTS = [
     ("pool_colour_truncates", "(csum[c] + n_pix / 2) / n_pix", "csum[c] / n_pix", 1),
     ("restore_cell_rounded", "(int64_t)(y / 3) * w1 + x / 3",
      "(int64_t)((y + 1) / 3) * w1 + x / 3", 1),
+    ("occluded_absolute_threshold", "(double)depth[p] - mean > tau * mean",
+     "(double)depth[p] - mean > tau", 1),
+    ("contour_counts_invalid_neighbours", "        if (!m[q]) continue;\n        const double diff",
+     "        const double diff", 1),
+    ("backproject_pixel_corner", "const double Xc = ((double)x + 0.5 - cx) * Z / fx;",
+     "const double Xc = ((double)x - cx) * Z / fx;", 1),
+    ("backproject_pose_not_inverted", "double s = pose[0 + i] * a;\n                s = s + pose[4 + i] * b;\n                s = s + pose[8 + i] * c;",
+     "double s = pose[4 * i] * a;\n                s = s + pose[4 * i + 1] * b;\n                s = s + pose[4 * i + 2] * c;", 1),
     ("restore_prefers_first_pass", "            if (valid[p]) {\n                depth2[p] = depth[p];",
      "            if (valid[p] && !mask1[q]) {\n                depth2[p] = depth[p];", 1),
 ]
