@@ -21,7 +21,9 @@ Further legs (``--legs``, all on by default):
 * ``fp16``     the Full-HD filter with FP16 range weights vs FP32;
 * ``two_stage`` the paper's two-stage configuration on the same Full-HD
   frame: projection, 3x3 pooling, r = 4 pass at a third of the
-  resolution, restore, r = 2 pass at full resolution (dense kernel);
+  resolution, restore, r = 2 pass at full resolution (dense kernel); and
+  the whole per-viewpoint pipeline with occluded-point removal before and
+  contour removal with back-projection to the world cloud after;
 * ``serving``  sixteen viewpoints (720p/1080p/4K, 50k-400k points, r = 5,
   FP16 range weights) with frames arriving on jittered 30 fps clocks:
   served (continuous batching) vs plain (one frame at a time), frames/s,
@@ -268,8 +270,9 @@ def fp16_leg(torch, dev, b, r, ss, sr, steps):
 
 
 def two_stage_leg(torch, dev, sets, cam, steps):
-    from paper_2601_01210_amd import (densify_two_stage, project,
-                                      two_stage_ws_bytes)
+    from paper_2601_01210_amd import (backproject, backproject_ws_bytes,
+                                      densify_two_stage, project,
+                                      remove_occluded, two_stage_ws_bytes)
     W, H = cam.width, cam.height
     params = (4, 2.0, 15.0, 2, 2.0, 15.0)
     wss = [torch.empty(two_stage_ws_bytes(H, W), dtype=torch.uint8, device=dev)
@@ -303,6 +306,41 @@ def two_stage_leg(torch, dev, sets, cam, steps):
         step(k, ev)
     torch.cuda.synchronize()
     valid = float(sets[0]["m"].float().mean())
+
+    # the whole per-viewpoint pipeline of the paper's system: projection,
+    # occluded-point removal (k = 3, tau = 0.1), the two-stage filter,
+    # contour removal (tau = 0.03) and back-projection to the world cloud
+    extra = []
+    for b in sets:
+        h_, w_ = b["d"].shape
+        extra.append(dict(
+            v2=torch.empty_like(b["v"]),
+            xyz=torch.empty((h_ * w_, 3), dtype=torch.float32, device=dev),
+            col=torch.empty((h_ * w_, 3), dtype=torch.uint8, device=dev),
+            cnt=torch.zeros(1, dtype=torch.int64, device=dev),
+            bws=torch.empty(backproject_ws_bytes(h_, w_), dtype=torch.uint8,
+                            device=dev)))
+
+    def full(k):
+        b, ws, x = sets[k % len(sets)], wss[k % len(sets)], extra[k % len(sets)]
+        project(b["pts"], cam.pose, cam.intrinsics(), W, H, zbuf=b["zbuf"],
+                depth=b["d"], valid=b["v"])
+        remove_occluded(b["d"], b["v"], 3, 0.1, out=x["v2"])
+        densify_two_stage(b["d"], x["v2"], b["rgb"], *params, out=b["out"],
+                          mask=b["m"], ws=ws)
+        backproject(b["out"], b["m"], b["rgb"], cam.pose, cam.intrinsics()[:4],
+                    0.03, xyz=x["xyz"], rgb_out=x["col"], count=x["cnt"],
+                    ws=x["bws"])
+
+    for k in range(10):
+        full(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        full(k)
+    torch.cuda.synchronize()
+    full_wall = time.perf_counter() - t0
+    n_points = int(extra[(steps - 1) % len(sets)]["cnt"].item())
     return {"frames_per_s": round(steps / wall, 1),
             "ms_per_frame": round(wall * 1e3 / steps, 4),
             "project_ms": round(float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), 4),
@@ -310,6 +348,12 @@ def two_stage_leg(torch, dev, sets, cam, steps):
             "radius1": params[0], "sigma_s1": params[1], "sigma_r1": params[2],
             "radius2": params[3], "sigma_s2": params[4], "sigma_r2": params[5],
             "valid_fraction_out": round(valid, 4),
+            "full_pipeline_frames_per_s": round(steps / full_wall, 1),
+            "full_pipeline_ms_per_frame": round(full_wall * 1e3 / steps, 4),
+            "full_pipeline_points_out": n_points,
+            "full_pipeline": "project, occluded-point removal (k=3, tau=0.1), "
+                             "two-stage filter, contour removal (tau=0.03), "
+                             "back-projection to the world cloud",
             "paper_ms_per_frame": PAPER_TWO_STAGE_MS,
             "paper_context": "Sec. 5 / Table 1: two-stage filter on Full-HD "
                              "frames, RTX 4090, PyTorch; another machine"}

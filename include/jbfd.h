@@ -349,6 +349,51 @@ jbfd_status jbfd_densify_two_stage(const float *sparse_depth,
                                    float *dense_depth, uint8_t *dense_valid,
                                    void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Occluded-point removal (Sec. 4.1: the merged depth map is averaged and
+ * samples lying well behind the average are dropped as surfaces the camera
+ * cannot see). For each valid pixel, mean = the mean of the valid depths in
+ * its (2k+1)^2 window (centre included, clipped at the border), summed in
+ * double in row-major order; valid_out = 0 when D - mean > tau * mean (in
+ * double), else valid_out = sparse_valid. The depth image is not changed.
+ *
+ * sparse_depth, sparse_valid  H*W (device); valid_out  H*W uint8 (device,
+ * may not alias sparse_valid); k 0 .. JBFD_OCCLUSION_MAX_K; tau finite >= 0.
+ */
+#define JBFD_OCCLUSION_MAX_K 8
+jbfd_status jbfd_remove_occluded(const float *sparse_depth,
+                                 const uint8_t *sparse_valid, int32_t H,
+                                 int32_t W, int32_t k, float tau,
+                                 uint8_t *valid_out, void *stream);
+
+/*
+ * Contour removal and back-projection to a coloured cloud in the world
+ * frame (Sec. 5: depths along object contours are removed by thresholding
+ * the depth gradient; Sec. 2: each viewpoint's coloured points go to the
+ * common world frame). A dense pixel is kept when dense_valid = 1 and its
+ * largest |D(n) - D(x)| over valid 4-neighbours n (in double) is at most
+ * tau * D(x) (tau = +inf keeps every valid pixel). A kept pixel (col, row)
+ * becomes p_c = ((col + 0.5 - cx) Z / fx, (row + 0.5 - cy) Z / fy, Z) and
+ * the world point R^T (p_c - t) for the camera-from-world pose [R|t], each
+ * coordinate evaluated in double without contraction and rounded once to
+ * float. Points are written in row-major pixel order.
+ *
+ * dense_depth, dense_valid, rgb_hwc  outputs of jbfd_densify (device)
+ * cam_from_world, K                  host, finite, fx and fy nonzero
+ * xyz        device float32, room for H*W*3 values
+ * rgb_out    device uint8, room for H*W*3 values
+ * count      device int64: the number of points written
+ * ws         device, 256-byte aligned, jbfd_backproject_ws_bytes(H, W)
+ *            bytes (else JBFD_ENOSPC)
+ */
+size_t jbfd_backproject_ws_bytes(int32_t H, int32_t W);
+jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_valid,
+                             const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                             const double cam_from_world[12],
+                             const jbfd_intrinsics *K, float tau, float *xyz,
+                             uint8_t *rgb_out, int64_t *count, void *ws,
+                             size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,8 @@ HIP kernels. There is no CPU fallback: if libjbfd.so is missing the calls
 raise.
 """
 from .binding import (BatchView, JbfdError, Precision,  # noqa: F401
-                      abi_version, batch_run, batch_table_bytes,
+                      abi_version, backproject, backproject_ws_bytes,
+                      batch_run, batch_table_bytes, remove_occluded,
                       batch_upload, densify, densify_backward,
                       densify_prepare, densify_two_stage, densify_workspace,
                       densify_ws_bytes, library_path, pool3, project,

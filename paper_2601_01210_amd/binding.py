@@ -106,6 +106,15 @@ def lib():
         L.jbfd_densify_two_stage.argtypes = [vp, vp, vp, i32, i32,
                                              C.POINTER(TwoStage), vp, vp, vp,
                                              sz, vp]
+        L.jbfd_remove_occluded.restype = C.c_int
+        L.jbfd_remove_occluded.argtypes = [vp, vp, i32, i32, i32, f32, vp, vp]
+        L.jbfd_backproject_ws_bytes.restype = sz
+        L.jbfd_backproject_ws_bytes.argtypes = [i32, i32]
+        L.jbfd_backproject.restype = C.c_int
+        L.jbfd_backproject.argtypes = [vp, vp, vp, i32, i32,
+                                       C.POINTER(C.c_double),
+                                       C.POINTER(Intrinsics), f32, vp, vp, vp,
+                                       vp, sz, vp]
         L.jbfd_batch_table_bytes.restype = sz
         L.jbfd_batch_table_bytes.argtypes = [i32]
         L.jbfd_batch_prepare.restype = C.c_int
@@ -503,3 +512,59 @@ def densify_two_stage(depth, valid, rgb, radius1: int, sigma_s1: float,
                                         C.byref(p), _ptr(out), _ptr(mask),
                                         _ptr(ws), ws.numel(), _stream(dev)))
     return out, mask
+
+
+# ---------------------------------------------------------------------------
+# occluded-point removal, contour removal and back-projection
+# ---------------------------------------------------------------------------
+
+def remove_occluded(depth, valid, k: int, tau: float, out=None):
+    """jbfd_remove_occluded: the valid mask with occluded samples dropped."""
+    torch = _torch()
+    h, w = depth.shape
+    _need(depth, torch.float32, (h, w), "depth")
+    _need(valid, torch.uint8, (h, w), "valid")
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.uint8, device=depth.device)
+    _need(out, torch.uint8, (h, w), "out")
+    _check(lib().jbfd_remove_occluded(_ptr(depth), _ptr(valid), h, w, int(k),
+                                      float(tau), _ptr(out),
+                                      _stream(depth.device)))
+    return out
+
+
+def backproject_ws_bytes(h: int, w: int) -> int:
+    return int(lib().jbfd_backproject_ws_bytes(h, w))
+
+
+def backproject(dense, mask, rgb, pose, intrinsics, tau: float = float("inf"),
+                xyz=None, rgb_out=None, count=None, ws=None):
+    """jbfd_backproject: returns (xyz float32 (H*W,3), rgb uint8 (H*W,3),
+    count int64 (1,)), all on the device; the first count rows are the
+    points in row-major pixel order (read count to slice on the host)."""
+    torch = _torch()
+    h, w = dense.shape
+    _need(dense, torch.float32, (h, w), "dense")
+    _need(mask, torch.uint8, (h, w), "mask")
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    dev = dense.device
+    if xyz is None:
+        xyz = torch.empty((h * w, 3), dtype=torch.float32, device=dev)
+    if rgb_out is None:
+        rgb_out = torch.empty((h * w, 3), dtype=torch.uint8, device=dev)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = torch.empty(max(backproject_ws_bytes(h, w), 256), dtype=torch.uint8,
+                         device=dev)
+    _need(xyz, torch.float32, (h * w, 3), "xyz")
+    _need(rgb_out, torch.uint8, (h * w, 3), "rgb_out")
+    _need(count, torch.int64, (1,), "count")
+    _need(ws, torch.uint8, None, "ws")
+    K = Intrinsics(float(intrinsics[0]), float(intrinsics[1]),
+                   float(intrinsics[2]), float(intrinsics[3]), int(w), int(h))
+    _check(lib().jbfd_backproject(_ptr(dense), _ptr(mask), _ptr(rgb), h, w,
+                                  _pose_array(pose), C.byref(K), float(tau),
+                                  _ptr(xyz), _ptr(rgb_out), _ptr(count),
+                                  _ptr(ws), ws.numel(), _stream(dev)))
+    return xyz, rgb_out, count

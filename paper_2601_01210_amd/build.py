@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjbfd.so")
 SOURCES = ["api.hip", "project.hip", "densify.hip", "backward.hip",
-           "stage2.hip"]
+           "stage2.hip", "cloud.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

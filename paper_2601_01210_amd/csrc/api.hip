@@ -283,6 +283,68 @@ jbfd_status jbfd_densify_two_stage(const float *sparse_depth,
                       "jbfd_densify_two_stage");
 }
 
+jbfd_status jbfd_remove_occluded(const float *sparse_depth,
+                                 const uint8_t *sparse_valid, int32_t H,
+                                 int32_t W, int32_t k, float tau,
+                                 uint8_t *valid_out, void *stream) {
+    if (!sparse_depth || !sparse_valid || !valid_out)
+        return fail(JBFD_EINVAL, "jbfd_remove_occluded: null buffer");
+    if (valid_out == sparse_valid)
+        return fail(JBFD_EINVAL, "jbfd_remove_occluded: valid_out aliases the input");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    if (k < 0 || k > JBFD_OCCLUSION_MAX_K)
+        return fail(JBFD_EINVAL, "jbfd_remove_occluded: k %d outside 0..%d", k,
+                    JBFD_OCCLUSION_MAX_K);
+    if (!isfinite(tau) || tau < 0.0f)
+        return fail(JBFD_EINVAL, "jbfd_remove_occluded: tau must be finite and >= 0");
+    return hip_status(jbfd::launch_remove_occluded(sparse_depth, sparse_valid, H, W,
+                                                   k, (double)tau, valid_out,
+                                                   (hipStream_t)stream),
+                      "jbfd_remove_occluded");
+}
+
+size_t jbfd_backproject_ws_bytes(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE) return 0;
+    return jbfd::backproject_ws_bytes(H, W);
+}
+
+jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_valid,
+                             const uint8_t *rgb_hwc, int32_t H, int32_t W,
+                             const double cam_from_world[12],
+                             const jbfd_intrinsics *K, float tau, float *xyz,
+                             uint8_t *rgb_out, int64_t *count, void *ws,
+                             size_t ws_bytes, void *stream) {
+    if (!dense_depth || !dense_valid || !rgb_hwc || !cam_from_world || !K || !xyz ||
+        !rgb_out || !count || !ws)
+        return fail(JBFD_EINVAL, "jbfd_backproject: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    if (K->width != W || K->height != H)
+        return fail(JBFD_EINVAL, "jbfd_backproject: intrinsics size %d x %d != image",
+                    K->width, K->height);
+    for (int t = 0; t < 12; ++t)
+        if (!isfinite(cam_from_world[t]))
+            return fail(JBFD_EINVAL, "jbfd_backproject: pose entry %d not finite", t);
+    if (!isfinite(K->fx) || !isfinite(K->fy) || !isfinite(K->cx) ||
+        !isfinite(K->cy) || K->fx == 0.0 || K->fy == 0.0)
+        return fail(JBFD_EINVAL, "jbfd_backproject: intrinsics not finite or zero focal");
+    if (isnan(tau) || tau < 0.0f)
+        return fail(JBFD_EINVAL, "jbfd_backproject: tau must be >= 0 or +inf");
+    if ((uintptr_t)ws & 255)
+        return fail(JBFD_EINVAL, "jbfd_backproject: workspace not aligned");
+    if (ws_bytes < jbfd::backproject_ws_bytes(H, W))
+        return fail(JBFD_ENOSPC, "jbfd_backproject: workspace %zu < %zu bytes",
+                    ws_bytes, jbfd::backproject_ws_bytes(H, W));
+    jbfd::Pose P;
+    for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
+    jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
+    return hip_status(jbfd::launch_backproject(dense_depth, dense_valid, rgb_hwc, H,
+                                               W, P, I, (double)tau, xyz, rgb_out,
+                                               count, ws, (hipStream_t)stream),
+                      "jbfd_backproject");
+}
+
 size_t jbfd_batch_table_bytes(int32_t n_views) {
     if (n_views < 1) return 0;
     return sizeof(jbfd::BatchHeader) + (size_t)n_views * sizeof(jbfd::BatchView);

@@ -124,6 +124,16 @@ hipError_t launch_two_stage(const float *D, const uint8_t *B, const uint8_t *rgb
                             const FilterParams &f2, float *out, uint8_t *mask,
                             void *ws, hipStream_t s);
 
+// Occluded-point removal, contour removal and back-projection (cloud.hip).
+hipError_t launch_remove_occluded(const float *D, const uint8_t *B, int32_t H,
+                                  int32_t W, int32_t k, double tau,
+                                  uint8_t *Bout, hipStream_t s);
+size_t backproject_ws_bytes(int32_t H, int32_t W);
+hipError_t launch_backproject(const float *D, const uint8_t *M, const uint8_t *rgb,
+                              int32_t H, int32_t W, const Pose &P, const Intr &K,
+                              double tau, float *xyz, uint8_t *rgb_out,
+                              int64_t *total, void *ws, hipStream_t s);
+
 hipError_t launch_batch(const void *d_table, int32_t max_radius,
                         jbfd_precision prec, hipStream_t s);
 hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,

@@ -248,3 +248,28 @@ def test_two_stage_and_dense_reject_bad_arguments(L):
     assert L.jbfd_densify(*dargs(2, 1, None)) == JBFD_EUNSUPPORTED
     assert L.jbfd_densify(*dargs(2, 0, fake)) == JBFD_EUNSUPPORTED
     assert L.jbfd_densify(*dargs(2, 0, None)[:-2], 4, None) == JBFD_EINVAL
+
+
+def test_occlusion_and_backproject_reject_bad_arguments(L):
+    from paper_2601_01210_amd.binding import JBFD_EINVAL, JBFD_ENOSPC
+    fake, other = C.c_void_p(0x1000), C.c_void_p(0x2000)
+    assert L.jbfd_remove_occluded(fake, fake, 8, 8, 2, 0.1, fake, None) == JBFD_EINVAL
+    assert L.jbfd_remove_occluded(fake, fake, 8, 8, 9, 0.1, other, None) == JBFD_EINVAL
+    assert L.jbfd_remove_occluded(fake, fake, 8, 8, 2, -0.1, other, None) == JBFD_EINVAL
+    assert L.jbfd_remove_occluded(fake, fake, 8, 8, 2, float("inf"), other,
+                                  None) == JBFD_EINVAL
+    pose = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    K = _K(8, 6)
+    ws = C.c_void_p(0x10000)
+    n = L.jbfd_backproject_ws_bytes(6, 8)
+    assert n >= 4
+    call = lambda k, tau, w_, nb: L.jbfd_backproject(fake, fake, fake, 6, 8, pose,
+                                                     C.byref(k), tau, fake, fake,
+                                                     fake, w_, nb, None)
+    assert call(K, 0.05, ws, n - 1 if n > 256 else 0) in (JBFD_ENOSPC, JBFD_EINVAL)
+    assert call(K, float("nan"), ws, n) == JBFD_EINVAL
+    assert call(_K(9, 6), 0.05, ws, n) == JBFD_EINVAL       # size mismatch
+    zero = _K(8, 6)
+    zero.fx = 0.0
+    assert call(zero, 0.05, ws, n) == JBFD_EINVAL
+    assert call(K, 0.05, C.c_void_p(0x10004), n) == JBFD_EINVAL
