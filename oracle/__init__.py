@@ -19,6 +19,8 @@ Functions (the C file documents the formulas and the passages they follow):
                           full-resolution second pass)
 * :func:`remove_occluded` Sec. 4.1 occluded-point removal
 * :func:`backproject`     Sec. 5 contour removal + Sec. 2 coloured cloud
+* :func:`motion_mask`, :func:`project_motion`
+                          Sec. 4.1 afterimage removal
 """
 from __future__ import annotations
 
@@ -95,6 +97,14 @@ def lib():
         L.oracle_backproject.restype = C.c_int64
         L.oracle_backproject.argtypes = [f32p, u8p, u8p, C.c_int32, C.c_int32,
                                          f64p, f64p, C.c_double, f32p, u8p]
+        i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
+        L.oracle_motion_mask.restype = None
+        L.oracle_motion_mask.argtypes = [u8p, u8p, C.c_int32, C.c_int32,
+                                         C.c_double, C.c_int32, u8p]
+        L.oracle_project_motion.restype = C.c_int64
+        L.oracle_project_motion.argtypes = [f32p, C.c_int64, i8p, C.c_int8,
+                                            u8p, f64p, f64p, C.c_int32,
+                                            C.c_int32, u64p, f32p, u8p]
         L.oracle_num_threads.restype = C.c_int
         L.oracle_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -280,3 +290,29 @@ def backproject(dense, mask, rgb, pose, intrinsics, tau: float):
                                  _c(intrinsics[:4], np.float64), float(tau),
                                  xyz, col)
     return xyz[:n].copy(), col[:n].copy()
+
+
+def motion_mask(rgb, rgb_prev, tau: float, k: int):
+    """Closed motion mask between two RGB frames (readings in oracle.c)."""
+    a = _c(rgb, np.uint8)
+    h, w = a.shape[:2]
+    out = np.empty((h, w), np.uint8)
+    lib().oracle_motion_mask(a.reshape(h, w, 3), _c(rgb_prev, np.uint8).reshape(h, w, 3),
+                             h, w, float(tau), int(k), out)
+    return out
+
+
+def project_motion(points, sweep, latest: int, motion, pose, intrinsics,
+                   width: int, height: int):
+    """project() with points of older sweeps dropped inside the motion
+    mask. Returns (keys, depth, valid, landed)."""
+    pts = _c(points, np.float32).reshape(-1, 3)
+    keys = np.empty((height, width), np.uint64)
+    depth = np.empty((height, width), np.float32)
+    valid = np.empty((height, width), np.uint8)
+    landed = lib().oracle_project_motion(pts, pts.shape[0], _c(sweep, np.int8),
+                                         int(latest), _c(motion, np.uint8),
+                                         _c(pose, np.float64).reshape(12),
+                                         _c(intrinsics[:4], np.float64), width,
+                                         height, keys, depth, valid)
+    return keys, depth, valid, int(landed)

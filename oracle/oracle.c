@@ -83,9 +83,14 @@ void oracle_set_num_threads(int n) {
  *
  * Returns the number of points that landed in the image.
  */
-int64_t oracle_project(const float *pts, int64_t n, const double *pose,
-                       const double *intr, int32_t width, int32_t height,
-                       uint64_t *keys, float *depth, uint8_t *valid) {
+/* Projection core. With sweep != NULL a point of an older sweep
+ * (sweep[i] != latest) whose pixel lies in the motion mask is dropped
+ * before it competes for the pixel (afterimage removal, below). */
+static int64_t project_core(const float *pts, int64_t n, const double *pose,
+                            const double *intr, int32_t width, int32_t height,
+                            uint64_t *keys, float *depth, uint8_t *valid,
+                            const int8_t *sweep, int8_t latest,
+                            const uint8_t *motion) {
     const double fx = intr[0], fy = intr[1], cx = intr[2], cy = intr[3];
     const int64_t npix = (int64_t)width * height;
     int64_t landed = 0;
@@ -119,6 +124,7 @@ int64_t oracle_project(const float *pts, int64_t n, const double *pose,
         if (zf == 0.0f || isinf(zf)) continue;
         const uint64_t key = ((uint64_t)float_bits(zf) << 32) | (uint64_t)(uint32_t)i;
         const int64_t pix = row * width + col;
+        if (sweep && sweep[i] != latest && motion[pix]) continue;
         if (key < keys[pix]) keys[pix] = key;
         ++landed;
     }
@@ -137,6 +143,13 @@ int64_t oracle_project(const float *pts, int64_t n, const double *pose,
         }
     }
     return landed;
+}
+
+int64_t oracle_project(const float *pts, int64_t n, const double *pose,
+                       const double *intr, int32_t width, int32_t height,
+                       uint64_t *keys, float *depth, uint8_t *valid) {
+    return project_core(pts, n, pose, intr, width, height, keys, depth, valid,
+                        NULL, 0, NULL);
 }
 
 /* 1/(2 sigma^2); an infinite sigma makes its Gaussian identically 1. */
@@ -605,4 +618,61 @@ int64_t oracle_backproject(const float *dense, const uint8_t *mask,
         }
     }
     return n;
+}
+
+/* ------------------------------------------------------------------------
+ * Afterimage removal (Sec. 4.1: moving regions are found from the colour
+ * change between consecutive RGB frames, thresholded at tau_m and closed
+ * morphologically; there, points not from the most recent LiDAR frame are
+ * discarded). Readings: motion where the squared RGB distance exceeds
+ * tau_m^2 (in double); closing with a (2k+1)^2 square, the dilation
+ * treating pixels outside the image as still, the erosion treating them as
+ * moving (so the closing never removes motion at the border); the most
+ * recent frame is the sweep with id `latest`.
+ * ---------------------------------------------------------------------- */
+
+void oracle_motion_mask(const uint8_t *rgb, const uint8_t *rgb_prev, int32_t h,
+                        int32_t w, double tau, int32_t k, uint8_t *mask) {
+    const int64_t n = (int64_t)h * w;
+    uint8_t *raw = (uint8_t *)malloc((size_t)n);
+    uint8_t *dil = (uint8_t *)malloc((size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+        int c = 0;
+        for (int ch = 0; ch < 3; ++ch) {
+            const int d = (int)rgb[3 * p + ch] - (int)rgb_prev[3 * p + ch];
+            c += d * d;
+        }
+        raw[p] = (uint8_t)((double)c > tau * tau);
+    }
+    for (int32_t y = 0; y < h; ++y)
+        for (int32_t x = 0; x < w; ++x) {
+            uint8_t any = 0;
+            for (int32_t yy = y - k; yy <= y + k; ++yy)
+                for (int32_t xx = x - k; xx <= x + k; ++xx)
+                    if (yy >= 0 && yy < h && xx >= 0 && xx < w &&
+                        raw[(int64_t)yy * w + xx])
+                        any = 1;
+            dil[(int64_t)y * w + x] = any;
+        }
+    for (int32_t y = 0; y < h; ++y)
+        for (int32_t x = 0; x < w; ++x) {
+            uint8_t all = 1;
+            for (int32_t yy = y - k; yy <= y + k; ++yy)
+                for (int32_t xx = x - k; xx <= x + k; ++xx)
+                    if (yy >= 0 && yy < h && xx >= 0 && xx < w &&
+                        !dil[(int64_t)yy * w + xx])
+                        all = 0;
+            mask[(int64_t)y * w + x] = all;
+        }
+    free(raw);
+    free(dil);
+}
+
+int64_t oracle_project_motion(const float *pts, int64_t n, const int8_t *sweep,
+                              int8_t latest, const uint8_t *motion,
+                              const double *pose, const double *intr,
+                              int32_t width, int32_t height, uint64_t *keys,
+                              float *depth, uint8_t *valid) {
+    return project_core(pts, n, pose, intr, width, height, keys, depth, valid,
+                        sweep, latest, motion);
 }

@@ -493,3 +493,42 @@ def arrival_times(rng: np.random.Generator, n_views: int, duration_s: float,
             t += rng.exponential(1.0 / rate_hz)
     out.sort()
     return out
+
+
+# --------------------------------------------------------------------------
+# a moving object: afterimages in merged sweeps
+# --------------------------------------------------------------------------
+
+def _shift_object(scene: Scene, obj: int, dx: float) -> Scene:
+    lo, hi = scene.lo.copy(), scene.hi.copy()
+    lo[obj, 0] += dx
+    hi[obj, 0] += dx
+    return dataclasses.replace(scene, lo=lo, hi=hi)
+
+
+def moving_view(rng: np.random.Generator, width=640, height=360,
+                n_objects=12, n_sweeps=3, n_beams=32, n_az=1024,
+                elev_deg=22.5, step_fraction=0.35):
+    """A textured scene whose nearest object moves sideways. The current
+    RGB frame and the last sweep see it at its current place; sweep s sees
+    it (n_sweeps - 1 - s) steps back; the previous RGB frame sees it one
+    step back. One step is ``step_fraction`` of the object's width. Returns
+    (frame at the current time with per-point sweep ids, previous RGB)."""
+    cam = Camera.pinhole(width, height)
+    scene = make_scene(rng, cam, n_objects, back_wall=20.0, textured=True)
+    obj = int(np.argmin(0.5 * (scene.lo[:, 2] + scene.hi[:, 2])))
+    step = step_fraction * float(scene.hi[obj, 0] - scene.lo[obj, 0])
+    rgb, gt = render(scene, cam, rng)
+    rgb_prev, _ = render(_shift_object(scene, obj, -step), cam, rng)
+    hfov = math.degrees(math.atan((width / 2.0) / cam.fx)) * 1.05
+    sweeps, ids = [], []
+    for s in range(n_sweeps):
+        seen = _shift_object(scene, obj, -step * (n_sweeps - 1 - s))
+        origin = _random_offset(rng, 0.3, exact=False)
+        pts = lidar_sweep(seen, rng, origin, n_beams, elev_deg, n_az,
+                          az_range_deg=(-hfov, hfov), az_phase=s / n_sweeps)
+        sweeps.append(pts)
+        ids.append(np.full(len(pts), s, np.int8))
+    frame = Frame(np.concatenate(sweeps, axis=0), rgb, cam, gt,
+                  np.concatenate(ids), **FILTER_SMALL)
+    return frame, rgb_prev

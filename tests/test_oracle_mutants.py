@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_SUITES = ["tests/test_oracle_project.py", "tests/test_oracle_filter.py",
               "tests/test_oracle_grad.py", "tests/test_oracle_two_stage.py",
-              "tests/test_oracle_cloud.py"]
+              "tests/test_oracle_cloud.py", "tests/test_oracle_afterimage.py"]
 
 # (name, text to replace, replacement, occurrences to replace or None = all)
 MUTANTS = [
@@ -52,6 +52,12 @@ MUTANTS = [
      "const double Xc = ((double)x - cx) * Z / fx;", 1),
     ("backproject_pose_not_inverted", "double s = pose[0 + i] * a;\n                s = s + pose[4 + i] * b;\n                s = s + pose[8 + i] * c;",
      "double s = pose[4 * i] * a;\n                s = s + pose[4 * i + 1] * b;\n                s = s + pose[4 * i + 2] * c;", 1),
+    ("motion_keeps_latest_only_outside", "if (sweep && sweep[i] != latest && motion[pix]) continue;",
+     "if (sweep && sweep[i] != latest && !motion[pix]) continue;", 1),
+    ("closing_erodes_at_border", "                    if (yy >= 0 && yy < h && xx >= 0 && xx < w &&\n                        !dil[(int64_t)yy * w + xx])",
+     "                    if (yy < 0 || yy >= h || xx < 0 || xx >= w ||\n                        !dil[(int64_t)yy * w + xx])", 1),
+    ("motion_threshold_not_squared", "raw[p] = (uint8_t)((double)c > tau * tau);",
+     "raw[p] = (uint8_t)((double)c > tau);", 1),
     ("restore_prefers_first_pass", "            if (valid[p]) {\n                depth2[p] = depth[p];",
      "            if (valid[p] && !mask1[q]) {\n                depth2[p] = depth[p];", 1),
 ]
