@@ -21,9 +21,11 @@ Further legs (``--legs``, all on by default):
 * ``fp16``     the Full-HD filter with FP16 range weights vs FP32;
 * ``two_stage`` the paper's two-stage configuration on the same Full-HD
   frame: projection, 3x3 pooling, r = 4 pass at a third of the
-  resolution, restore, r = 2 pass at full resolution (dense kernel); and
-  the whole per-viewpoint pipeline with occluded-point removal before and
-  contour removal with back-projection to the world cloud after;
+  resolution, restore, r = 2 pass at full resolution (dense kernel);
+* ``system``   the whole per-viewpoint pipeline on a Full-HD frame with a
+  moving object: afterimage removal (motion mask, motion-aware
+  projection), occluded-point removal, the two-stage filter, contour
+  removal and back-projection to the world cloud;
 * ``serving``  sixteen viewpoints (720p/1080p/4K, 50k-400k points, r = 5,
   FP16 range weights) with frames arriving on jittered 30 fps clocks:
   served (continuous batching) vs plain (one frame at a time), frames/s,
@@ -57,7 +59,7 @@ FLOPS_PER_PAIR = 14                 # per (output pixel, valid sample) pair
 ROTATE_BYTES = 600 << 20            # > 512 MB of distinct buffers
 FHD = 1920 * 1080
 LATENCY_TARGET_MS = 33.0
-LEGS = ("batched", "fp16", "two_stage", "serving", "fit")
+LEGS = ("batched", "fp16", "two_stage", "system", "serving", "fit")
 # Sec. 5 and Table 1: the paper's own per-frame time for its two-stage
 # filter on Full-HD frames (context, another machine)
 PAPER_TWO_STAGE_MS = 23.0
@@ -137,9 +139,17 @@ def _fit_view(seed):
     return S.small_view(np.random.default_rng(seed), 1920, 1080)
 
 
+def _moving_view(seed):
+    """Full-HD, 40 objects, three 32-beam sweeps; the nearest object moves."""
+    return S.moving_view(np.random.default_rng(seed), 1920, 1080, n_objects=40,
+                         n_az=2048)
+
+
 def _gen(job):
     kind, arg = job
-    return S.serving_view(arg) if kind == "serve" else _fit_view(arg)
+    if kind == "serve":
+        return S.serving_view(arg)
+    return _moving_view(arg) if kind == "moving" else _fit_view(arg)
 
 
 def generate(args):
@@ -150,6 +160,8 @@ def generate(args):
     if "batched" in args.legs:
         out["batch"] = S.batch_views(S.seeded(3))
     jobs = []
+    if "system" in args.legs:
+        jobs.append(("moving", int(S.seeded(7).integers(0, 2 ** 63))))
     if "serving" in args.legs:
         out["serve_specs"] = S.serving_specs(S.seeded(4))
         jobs += [("serve", s) for s in out["serve_specs"]]
@@ -162,6 +174,8 @@ def generate(args):
             res = pool.map(_gen, jobs, chunksize=1)
         out["serve"] = [f for (k, _), f in zip(jobs, res) if k == "serve"]
         out["fit"] = [f for (k, _), f in zip(jobs, res) if k == "fit"]
+        out["moving"] = next((f for (k, _), f in zip(jobs, res) if k == "moving"),
+                             None)
     out["seconds"] = round(time.time() - t, 2)
     return out
 
@@ -270,9 +284,8 @@ def fp16_leg(torch, dev, b, r, ss, sr, steps):
 
 
 def two_stage_leg(torch, dev, sets, cam, steps):
-    from paper_2601_01210_amd import (backproject, backproject_ws_bytes,
-                                      densify_two_stage, project,
-                                      remove_occluded, two_stage_ws_bytes)
+    from paper_2601_01210_amd import (densify_two_stage, project,
+                                      two_stage_ws_bytes)
     W, H = cam.width, cam.height
     params = (4, 2.0, 15.0, 2, 2.0, 15.0)
     wss = [torch.empty(two_stage_ws_bytes(H, W), dtype=torch.uint8, device=dev)
@@ -306,41 +319,6 @@ def two_stage_leg(torch, dev, sets, cam, steps):
         step(k, ev)
     torch.cuda.synchronize()
     valid = float(sets[0]["m"].float().mean())
-
-    # the whole per-viewpoint pipeline of the paper's system: projection,
-    # occluded-point removal (k = 3, tau = 0.1), the two-stage filter,
-    # contour removal (tau = 0.03) and back-projection to the world cloud
-    extra = []
-    for b in sets:
-        h_, w_ = b["d"].shape
-        extra.append(dict(
-            v2=torch.empty_like(b["v"]),
-            xyz=torch.empty((h_ * w_, 3), dtype=torch.float32, device=dev),
-            col=torch.empty((h_ * w_, 3), dtype=torch.uint8, device=dev),
-            cnt=torch.zeros(1, dtype=torch.int64, device=dev),
-            bws=torch.empty(backproject_ws_bytes(h_, w_), dtype=torch.uint8,
-                            device=dev)))
-
-    def full(k):
-        b, ws, x = sets[k % len(sets)], wss[k % len(sets)], extra[k % len(sets)]
-        project(b["pts"], cam.pose, cam.intrinsics(), W, H, zbuf=b["zbuf"],
-                depth=b["d"], valid=b["v"])
-        remove_occluded(b["d"], b["v"], 3, 0.1, out=x["v2"])
-        densify_two_stage(b["d"], x["v2"], b["rgb"], *params, out=b["out"],
-                          mask=b["m"], ws=ws)
-        backproject(b["out"], b["m"], b["rgb"], cam.pose, cam.intrinsics()[:4],
-                    0.03, xyz=x["xyz"], rgb_out=x["col"], count=x["cnt"],
-                    ws=x["bws"])
-
-    for k in range(10):
-        full(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        full(k)
-    torch.cuda.synchronize()
-    full_wall = time.perf_counter() - t0
-    n_points = int(extra[(steps - 1) % len(sets)]["cnt"].item())
     return {"frames_per_s": round(steps / wall, 1),
             "ms_per_frame": round(wall * 1e3 / steps, 4),
             "project_ms": round(float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), 4),
@@ -348,15 +326,95 @@ def two_stage_leg(torch, dev, sets, cam, steps):
             "radius1": params[0], "sigma_s1": params[1], "sigma_r1": params[2],
             "radius2": params[3], "sigma_s2": params[4], "sigma_r2": params[5],
             "valid_fraction_out": round(valid, 4),
-            "full_pipeline_frames_per_s": round(steps / full_wall, 1),
-            "full_pipeline_ms_per_frame": round(full_wall * 1e3 / steps, 4),
-            "full_pipeline_points_out": n_points,
-            "full_pipeline": "project, occluded-point removal (k=3, tau=0.1), "
-                             "two-stage filter, contour removal (tau=0.03), "
-                             "back-projection to the world cloud",
             "paper_ms_per_frame": PAPER_TWO_STAGE_MS,
             "paper_context": "Sec. 5 / Table 1: two-stage filter on Full-HD "
                              "frames, RTX 4090, PyTorch; another machine"}
+
+
+def system_leg(torch, dev, moving, steps):
+    """The whole per-viewpoint pipeline of the paper's system on a Full-HD
+    frame with a moving object: motion mask from the previous RGB frame
+    (tau = 60, 5x5 closing), projection that drops older sweeps' points in
+    it, occluded-point removal (k = 3, tau = 0.1), the two-stage filter,
+    contour removal (tau = 0.03) and back-projection to the world cloud."""
+    from paper_2601_01210_amd import (backproject, backproject_ws_bytes,
+                                      densify_two_stage, motion_mask,
+                                      motion_mask_ws_bytes, project_motion,
+                                      remove_occluded, two_stage_ws_bytes)
+    frame, prev = moving
+    cam = frame.camera
+    W, H = cam.width, cam.height
+    params = (4, 2.0, 15.0, 2, 2.0, 15.0)
+    n = len(frame.points)
+    per_set = n * 13 + H * W * (3 + 3 + 1 + 8 + 4 + 1 + 1 + 4 + 1 + 12 + 3 + 2) + \
+        two_stage_ws_bytes(H, W) + backproject_ws_bytes(H, W)
+    n_sets = max(2, math.ceil(ROTATE_BYTES / per_set))
+    e = lambda shape, dt: torch.empty(shape, dtype=dt, device=dev)
+    u8, f32 = torch.uint8, torch.float32
+    host = {k: torch.from_numpy(v) for k, v in
+            dict(pts=frame.points, sweep=frame.sweep_id, rgb=frame.rgb,
+                 prev=prev).items()}
+    sets = []
+    for _ in range(n_sets):
+        b = {k: v.to(dev) for k, v in host.items()}
+        b.update(motion=e((H, W), u8), mws=e(motion_mask_ws_bytes(H, W), u8),
+                 zbuf=e((H, W), torch.int64), d=e((H, W), f32), v=e((H, W), u8),
+                 v2=e((H, W), u8), out=e((H, W), f32), m=e((H, W), u8),
+                 ws=e(two_stage_ws_bytes(H, W), u8), xyz=e((H * W, 3), f32),
+                 col=e((H * W, 3), u8), cnt=torch.zeros(1, dtype=torch.int64, device=dev),
+                 bws=e(backproject_ws_bytes(H, W), u8))
+        sets.append(b)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(k, ev=None):
+        b = sets[k % n_sets]
+        mark = (lambda i: ev[i].record(stream)) if ev is not None else (lambda i: None)
+        mark(0)
+        motion_mask(b["rgb"], b["prev"], 60.0, 2, out=b["motion"], ws=b["mws"])
+        mark(1)
+        project_motion(b["pts"], b["sweep"], 2, b["motion"], cam.pose,
+                       cam.intrinsics()[:4], W, H, zbuf=b["zbuf"], depth=b["d"],
+                       valid=b["v"])
+        mark(2)
+        remove_occluded(b["d"], b["v"], 3, 0.1, out=b["v2"])
+        mark(3)
+        densify_two_stage(b["d"], b["v2"], b["rgb"], *params, out=b["out"],
+                          mask=b["m"], ws=b["ws"])
+        mark(4)
+        backproject(b["out"], b["m"], b["rgb"], cam.pose, cam.intrinsics()[:4],
+                    0.03, xyz=b["xyz"], rgb_out=b["col"], count=b["cnt"],
+                    ws=b["bws"])
+        mark(5)
+
+    for k in range(10):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)]
+           for _ in range(max(steps // 2, 10))]
+    for k, ev in enumerate(evs):
+        step(k, ev)
+    torch.cuda.synchronize()
+    stage = lambda i: round(float(np.mean([x[i].elapsed_time(x[i + 1]) for x in evs])), 4)
+    b = sets[0]
+    return {"frames_per_s": round(steps / wall, 1),
+            "ms_per_frame": round(wall * 1e3 / steps, 4),
+            "stage_ms": {"motion_mask": stage(0), "project_motion": stage(1),
+                         "remove_occluded": stage(2), "two_stage": stage(3),
+                         "contour_backproject": stage(4)},
+            "points": n, "moving_pixel_fraction": round(float(b["motion"].float().mean()), 4),
+            "sparse_valid_pixels": int(b["v"].sum()),
+            "after_occlusion_pixels": int(b["v2"].sum()),
+            "points_out": int(b["cnt"].item()),
+            "buffer_sets": n_sets,
+            "pipeline": "motion mask (tau=60, k=2), motion-aware projection, "
+                        "occluded-point removal (k=3, tau=0.1), two-stage "
+                        "filter, contour removal (tau=0.03), back-projection "
+                        "to the world cloud"}
 
 
 def serving_leg(torch, dev, frames, args):
@@ -678,6 +736,11 @@ def main():
         print(f"[bench] two-stage: {legs['two_stage_fullhd']}", flush=True)
     del sets
     torch.cuda.synchronize()
+    if "system" in args.legs:
+        legs["system_fullhd"] = system_leg(torch, dev, work["moving"],
+                                           max(args.steps // 2, 20))
+        print(f"[bench] system: {legs['system_fullhd']}", flush=True)
+        torch.cuda.synchronize()
     if "batched" in args.legs:
         legs["batched"] = batched_leg(torch, dev, work["batch"],
                                       max(args.steps // 4, 10))

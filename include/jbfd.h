@@ -394,6 +394,38 @@ jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_vali
                              uint8_t *rgb_out, int64_t *count, void *ws,
                              size_t ws_bytes, void *stream);
 
+/*
+ * Afterimage removal (Sec. 4.1: moving regions are found from the colour
+ * change between consecutive RGB frames, thresholded and closed
+ * morphologically; there, LiDAR points not from the most recent frame are
+ * discarded before the depth image is formed).
+ *
+ * jbfd_motion_mask: mask = closing of [squared RGB distance between rgb and
+ * rgb_prev > tau^2] with a (2k+1)x(2k+1) square; the dilation treats
+ * pixels outside the image as still and the erosion treats them as moving,
+ * so the closing never removes motion at the border. ws: device, 256-byte
+ * aligned, jbfd_motion_mask_ws_bytes(H, W) bytes (else JBFD_ENOSPC).
+ * k 0 .. JBFD_MOTION_MAX_K; tau finite >= 0.
+ *
+ * jbfd_project_motion: jbfd_project in which a point whose sweep id
+ * (sweep_ids[i], device int8) differs from `latest` is dropped when its
+ * pixel lies in `motion` (device, K->height x K->width); all else as
+ * jbfd_project.
+ */
+#define JBFD_MOTION_MAX_K 16
+size_t jbfd_motion_mask_ws_bytes(int32_t H, int32_t W);
+jbfd_status jbfd_motion_mask(const uint8_t *rgb_hwc, const uint8_t *rgb_prev_hwc,
+                             int32_t H, int32_t W, float tau, int32_t k,
+                             uint8_t *mask, void *ws, size_t ws_bytes,
+                             void *stream);
+jbfd_status jbfd_project_motion(const float *pts_xyz, int64_t n,
+                                const int8_t *sweep_ids, int8_t latest,
+                                const uint8_t *motion,
+                                const double cam_from_world[12],
+                                const jbfd_intrinsics *K, uint64_t *zbuf,
+                                float *sparse_depth, uint8_t *sparse_valid,
+                                void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,16 @@ def lib():
                                        C.POINTER(C.c_double),
                                        C.POINTER(Intrinsics), f32, vp, vp, vp,
                                        vp, sz, vp]
+        L.jbfd_motion_mask_ws_bytes.restype = sz
+        L.jbfd_motion_mask_ws_bytes.argtypes = [i32, i32]
+        L.jbfd_motion_mask.restype = C.c_int
+        L.jbfd_motion_mask.argtypes = [vp, vp, i32, i32, f32, i32, vp, vp, sz,
+                                       vp]
+        L.jbfd_project_motion.restype = C.c_int
+        L.jbfd_project_motion.argtypes = [vp, i64, vp, C.c_int8, vp,
+                                          C.POINTER(C.c_double),
+                                          C.POINTER(Intrinsics), vp, vp, vp,
+                                          vp]
         L.jbfd_batch_table_bytes.restype = sz
         L.jbfd_batch_table_bytes.argtypes = [i32]
         L.jbfd_batch_prepare.restype = C.c_int
@@ -568,3 +578,66 @@ def backproject(dense, mask, rgb, pose, intrinsics, tau: float = float("inf"),
                                   _ptr(xyz), _ptr(rgb_out), _ptr(count),
                                   _ptr(ws), ws.numel(), _stream(dev)))
     return xyz, rgb_out, count
+
+
+# ---------------------------------------------------------------------------
+# afterimage removal
+# ---------------------------------------------------------------------------
+
+def motion_mask_ws_bytes(h: int, w: int) -> int:
+    return int(lib().jbfd_motion_mask_ws_bytes(h, w))
+
+
+def motion_mask(rgb, rgb_prev, tau: float, k: int, out=None, ws=None):
+    """jbfd_motion_mask: closed mask of pixels whose colour changed by more
+    than tau between two (H,W,3) uint8 frames."""
+    torch = _torch()
+    h, w = rgb.shape[:2]
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    _need(rgb_prev, torch.uint8, (h, w, 3), "rgb_prev")
+    dev = rgb.device
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    if ws is None:
+        ws = torch.empty(max(motion_mask_ws_bytes(h, w), 256), dtype=torch.uint8,
+                         device=dev)
+    _need(out, torch.uint8, (h, w), "out")
+    _need(ws, torch.uint8, None, "ws")
+    _check(lib().jbfd_motion_mask(_ptr(rgb), _ptr(rgb_prev), h, w, float(tau),
+                                  int(k), _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream(dev)))
+    return out
+
+
+def project_motion(points, sweep, latest: int, motion, pose,
+                   intrinsics: Sequence[float], width: int, height: int,
+                   zbuf=None, depth=None, valid=None, want_sparse: bool = True):
+    """jbfd_project_motion: project() with points of sweeps other than
+    ``latest`` dropped where ``motion`` (H,W uint8) is set. ``sweep`` is an
+    (N,) int8 device tensor."""
+    torch = _torch()
+    _need(points, torch.float32, None, "points")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (N, 3)")
+    n = int(points.shape[0])
+    _need(sweep, torch.int8, (n,), "sweep")
+    _need(motion, torch.uint8, (height, width), "motion")
+    dev = points.device
+    if zbuf is None:
+        zbuf = torch.empty((height, width), dtype=torch.int64, device=dev)
+    _need(zbuf, torch.int64, (height, width), "zbuf")
+    if want_sparse:
+        if depth is None:
+            depth = torch.empty((height, width), dtype=torch.float32, device=dev)
+        if valid is None:
+            valid = torch.empty((height, width), dtype=torch.uint8, device=dev)
+        _need(depth, torch.float32, (height, width), "depth")
+        _need(valid, torch.uint8, (height, width), "valid")
+    K = Intrinsics(float(intrinsics[0]), float(intrinsics[1]),
+                   float(intrinsics[2]), float(intrinsics[3]), int(width),
+                   int(height))
+    _check(lib().jbfd_project_motion(_ptr(points), n, _ptr(sweep), int(latest),
+                                     _ptr(motion), _pose_array(pose), C.byref(K),
+                                     _ptr(zbuf), _ptr(depth), _ptr(valid),
+                                     _stream(dev)))
+    return zbuf, depth, valid

@@ -345,6 +345,66 @@ jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_vali
                       "jbfd_backproject");
 }
 
+size_t jbfd_motion_mask_ws_bytes(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE) return 0;
+    return jbfd::motion_mask_ws_bytes(H, W);
+}
+
+jbfd_status jbfd_motion_mask(const uint8_t *rgb_hwc, const uint8_t *rgb_prev_hwc,
+                             int32_t H, int32_t W, float tau, int32_t k,
+                             uint8_t *mask, void *ws, size_t ws_bytes,
+                             void *stream) {
+    if (!rgb_hwc || !rgb_prev_hwc || !mask || !ws)
+        return fail(JBFD_EINVAL, "jbfd_motion_mask: null buffer");
+    jbfd_status st = check_image(H, W);
+    if (st != JBFD_OK) return st;
+    if (k < 0 || k > JBFD_MOTION_MAX_K)
+        return fail(JBFD_EINVAL, "jbfd_motion_mask: k %d outside 0..%d", k,
+                    JBFD_MOTION_MAX_K);
+    if (!isfinite(tau) || tau < 0.0f)
+        return fail(JBFD_EINVAL, "jbfd_motion_mask: tau must be finite and >= 0");
+    if ((uintptr_t)ws & 255)
+        return fail(JBFD_EINVAL, "jbfd_motion_mask: workspace not aligned");
+    if (ws_bytes < jbfd::motion_mask_ws_bytes(H, W))
+        return fail(JBFD_ENOSPC, "jbfd_motion_mask: workspace %zu < %zu bytes",
+                    ws_bytes, jbfd::motion_mask_ws_bytes(H, W));
+    return hip_status(jbfd::launch_motion_mask(rgb_hwc, rgb_prev_hwc, H, W,
+                                               (double)tau, k, mask, ws,
+                                               (hipStream_t)stream),
+                      "jbfd_motion_mask");
+}
+
+jbfd_status jbfd_project_motion(const float *pts_xyz, int64_t n,
+                                const int8_t *sweep_ids, int8_t latest,
+                                const uint8_t *motion,
+                                const double cam_from_world[12],
+                                const jbfd_intrinsics *K, uint64_t *zbuf,
+                                float *sparse_depth, uint8_t *sparse_valid,
+                                void *stream) {
+    if (!cam_from_world || !K || !zbuf || !motion)
+        return fail(JBFD_EINVAL, "jbfd_project_motion: null pose, intrinsics, zbuf or mask");
+    if (n < 0 || n >= ((int64_t)1 << 32))
+        return fail(JBFD_EINVAL, "jbfd_project_motion: n = %lld outside 0..2^32-1",
+                    (long long)n);
+    if (n > 0 && (!pts_xyz || !sweep_ids))
+        return fail(JBFD_EINVAL, "jbfd_project_motion: null points or sweep ids");
+    jbfd_status st = check_image(K->height, K->width);
+    if (st != JBFD_OK) return st;
+    for (int t = 0; t < 12; ++t)
+        if (!isfinite(cam_from_world[t]))
+            return fail(JBFD_EINVAL, "jbfd_project_motion: pose entry %d not finite", t);
+    if (!isfinite(K->fx) || !isfinite(K->fy) || !isfinite(K->cx) ||
+        !isfinite(K->cy))
+        return fail(JBFD_EINVAL, "jbfd_project_motion: intrinsics not finite");
+    jbfd::Pose P;
+    for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
+    jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
+    return hip_status(jbfd::launch_project_motion(pts_xyz, n, sweep_ids, latest,
+                                                  motion, P, I, zbuf, sparse_depth,
+                                                  sparse_valid, (hipStream_t)stream),
+                      "jbfd_project_motion");
+}
+
 size_t jbfd_batch_table_bytes(int32_t n_views) {
     if (n_views < 1) return 0;
     return sizeof(jbfd::BatchHeader) + (size_t)n_views * sizeof(jbfd::BatchView);

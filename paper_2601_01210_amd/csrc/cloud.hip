@@ -203,3 +203,71 @@ hipError_t launch_backproject(const float *D, const uint8_t *M, const uint8_t *r
 }
 
 }  // namespace jbfd
+
+namespace jbfd {
+
+// ---------------------------------------------------------------------------
+// afterimage removal: closed motion mask (Sec. 4.1)
+// ---------------------------------------------------------------------------
+
+// raw[p] = squared RGB distance between the frames > tau^2 (in double)
+__global__ __launch_bounds__(256) void k_motion_raw(const uint8_t *__restrict__ a,
+                                                    const uint8_t *__restrict__ b,
+                                                    int64_t n, double tau2,
+                                                    uint8_t *__restrict__ raw) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += stride) {
+        int c = 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const int d = (int)a[3 * p + ch] - (int)b[3 * p + ch];
+            c += d * d;
+        }
+        raw[p] = (uint8_t)((double)c > tau2);
+    }
+}
+
+// One separable pass of the square closing over the in-image part of each
+// window, along rows (ROWS) or columns: OR (dilation) or AND (erosion).
+template <bool ROWS, bool OR>
+__global__ __launch_bounds__(256) void k_morph_pass(const uint8_t *__restrict__ in,
+                                                    int H, int W, int k,
+                                                    uint8_t *__restrict__ out) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += stride) {
+        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+        const int c = ROWS ? x : y, len = ROWS ? W : H;
+        const int lo = max(c - k, 0), hi = min(c + k, len - 1);
+        uint8_t r = OR ? 0 : 1;
+        for (int j = lo; j <= hi; ++j) {
+            const uint8_t v = ROWS ? in[(int64_t)y * W + j] : in[(int64_t)j * W + x];
+            r = OR ? (uint8_t)(r | v) : (uint8_t)(r & v);
+        }
+        out[p] = r;
+    }
+}
+
+size_t motion_mask_ws_bytes(int32_t H, int32_t W) {
+    return 2 * align256((size_t)H * W);
+}
+
+hipError_t launch_motion_mask(const uint8_t *rgb, const uint8_t *rgb_prev,
+                              int32_t H, int32_t W, double tau, int32_t k,
+                              uint8_t *mask, void *ws, hipStream_t s) {
+    const int64_t n = (int64_t)H * W;
+    uint8_t *t0 = static_cast<uint8_t *>(ws);
+    uint8_t *t1 = t0 + align256((size_t)n);
+    int64_t g = (n + 255) / 256;
+    const int grid = (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
+    k_motion_raw<<<grid, 256, 0, s>>>(rgb, rgb_prev, n, tau * tau, t0);
+    k_morph_pass<true, true><<<grid, 256, 0, s>>>(t0, H, W, k, t1);    // dilate rows
+    k_morph_pass<false, true><<<grid, 256, 0, s>>>(t1, H, W, k, t0);   // dilate cols
+    k_morph_pass<true, false><<<grid, 256, 0, s>>>(t0, H, W, k, t1);   // erode rows
+    k_morph_pass<false, false><<<grid, 256, 0, s>>>(t1, H, W, k, mask); // erode cols
+    return hipGetLastError();
+}
+
+}  // namespace jbfd

@@ -86,6 +86,24 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ pts,
     }
 }
 
+// k_project for a merged cloud of several sweeps: a point from a sweep other
+// than `latest` that lands in a moving pixel of `motion` is dropped.
+__global__ __launch_bounds__(256) void k_project_motion(
+    const float *__restrict__ pts, int64_t n, const int8_t *__restrict__ sweep,
+    int8_t latest, const uint8_t *__restrict__ motion, Pose P, Intr K,
+    unsigned long long *__restrict__ keys) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride) {
+        unsigned long long key;
+        int64_t pix;
+        if (!project_one(pts, i, P.m, K.fx, K.fy, K.cx, K.cy, K.w, K.h, key, pix))
+            continue;
+        if (sweep[i] != latest && motion[pix]) continue;
+        atomicMin(keys + pix, key);
+    }
+}
+
 // Decode pixels [p0, min(p0+4, npix)): two 16-byte key loads, one 16-byte
 // depth store and one 4-byte mask store when aligned, else per pixel.
 __device__ inline void decode4(const uint64_t *__restrict__ keys, int64_t npix,
@@ -216,6 +234,21 @@ hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
     if (n > 0)
         k_project<<<grid_for(n, 256), 256, 0, s>>>(
             pts, n, pose, K, reinterpret_cast<unsigned long long *>(zbuf));
+    if (depth || valid)
+        k_decode<<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *sweep,
+                                 int8_t latest, const uint8_t *motion,
+                                 const Pose &P, const Intr &K, uint64_t *zbuf,
+                                 float *depth, uint8_t *valid, hipStream_t s) {
+    const int64_t npix = (int64_t)K.w * K.h;
+    k_fill_keys<<<grid_for(npix, 512), 256, 0, s>>>(zbuf, npix);
+    if (n > 0)
+        k_project_motion<<<grid_for(n, 256), 256, 0, s>>>(
+            pts, n, sweep, latest, motion, P, K,
+            reinterpret_cast<unsigned long long *>(zbuf));
     if (depth || valid)
         k_decode<<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
     return hipGetLastError();
