@@ -339,7 +339,7 @@ def system_leg(torch, dev, moving, steps):
     contour removal (tau = 0.03) and back-projection to the world cloud."""
     from paper_2601_01210_amd import (backproject, backproject_ws_bytes,
                                       densify_two_stage, motion_mask,
-                                      motion_mask_ws_bytes, project_motion,
+                                      project_motion,
                                       remove_occluded, two_stage_ws_bytes)
     frame, prev = moving
     cam = frame.camera
@@ -357,7 +357,7 @@ def system_leg(torch, dev, moving, steps):
     sets = []
     for _ in range(n_sets):
         b = {k: v.to(dev) for k, v in host.items()}
-        b.update(motion=e((H, W), u8), mws=e(motion_mask_ws_bytes(H, W), u8),
+        b.update(motion=e((H, W), u8),
                  zbuf=e((H, W), torch.int64), d=e((H, W), f32), v=e((H, W), u8),
                  v2=e((H, W), u8), out=e((H, W), f32), m=e((H, W), u8),
                  ws=e(two_stage_ws_bytes(H, W), u8), xyz=e((H * W, 3), f32),
@@ -370,7 +370,7 @@ def system_leg(torch, dev, moving, steps):
         b = sets[k % n_sets]
         mark = (lambda i: ev[i].record(stream)) if ev is not None else (lambda i: None)
         mark(0)
-        motion_mask(b["rgb"], b["prev"], 60.0, 2, out=b["motion"], ws=b["mws"])
+        motion_mask(b["rgb"], b["prev"], 60.0, 2, out=b["motion"])
         mark(1)
         project_motion(b["pts"], b["sweep"], 2, b["motion"], cam.pose,
                        cam.intrinsics()[:4], W, H, zbuf=b["zbuf"], depth=b["d"],

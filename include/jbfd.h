@@ -403,9 +403,10 @@ jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_vali
  * jbfd_motion_mask: mask = closing of [squared RGB distance between rgb and
  * rgb_prev > tau^2] with a (2k+1)x(2k+1) square; the dilation treats
  * pixels outside the image as still and the erosion treats them as moving,
- * so the closing never removes motion at the border. ws: device, 256-byte
- * aligned, jbfd_motion_mask_ws_bytes(H, W) bytes (else JBFD_ENOSPC).
- * k 0 .. JBFD_MOTION_MAX_K; tau finite >= 0.
+ * so the closing never removes motion at the border. rgb_hwc, rgb_prev_hwc:
+ * device H x W x 3 uint8; mask: device H x W uint8 (1 = moving), written
+ * in full. k 0 .. JBFD_MOTION_MAX_K; tau finite >= 0; else JBFD_EINVAL.
+ * Needs no workspace.
  *
  * jbfd_project_motion: jbfd_project in which a point whose sweep id
  * (sweep_ids[i], device int8) differs from `latest` is dropped when its
@@ -413,11 +414,9 @@ jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_vali
  * jbfd_project.
  */
 #define JBFD_MOTION_MAX_K 16
-size_t jbfd_motion_mask_ws_bytes(int32_t H, int32_t W);
 jbfd_status jbfd_motion_mask(const uint8_t *rgb_hwc, const uint8_t *rgb_prev_hwc,
                              int32_t H, int32_t W, float tau, int32_t k,
-                             uint8_t *mask, void *ws, size_t ws_bytes,
-                             void *stream);
+                             uint8_t *mask, void *stream);
 jbfd_status jbfd_project_motion(const float *pts_xyz, int64_t n,
                                 const int8_t *sweep_ids, int8_t latest,
                                 const uint8_t *motion,

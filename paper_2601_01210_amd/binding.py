@@ -115,11 +115,8 @@ def lib():
                                        C.POINTER(C.c_double),
                                        C.POINTER(Intrinsics), f32, vp, vp, vp,
                                        vp, sz, vp]
-        L.jbfd_motion_mask_ws_bytes.restype = sz
-        L.jbfd_motion_mask_ws_bytes.argtypes = [i32, i32]
         L.jbfd_motion_mask.restype = C.c_int
-        L.jbfd_motion_mask.argtypes = [vp, vp, i32, i32, f32, i32, vp, vp, sz,
-                                       vp]
+        L.jbfd_motion_mask.argtypes = [vp, vp, i32, i32, f32, i32, vp, vp]
         L.jbfd_project_motion.restype = C.c_int
         L.jbfd_project_motion.argtypes = [vp, i64, vp, C.c_int8, vp,
                                           C.POINTER(C.c_double),
@@ -584,11 +581,7 @@ def backproject(dense, mask, rgb, pose, intrinsics, tau: float = float("inf"),
 # afterimage removal
 # ---------------------------------------------------------------------------
 
-def motion_mask_ws_bytes(h: int, w: int) -> int:
-    return int(lib().jbfd_motion_mask_ws_bytes(h, w))
-
-
-def motion_mask(rgb, rgb_prev, tau: float, k: int, out=None, ws=None):
+def motion_mask(rgb, rgb_prev, tau: float, k: int, out=None):
     """jbfd_motion_mask: closed mask of pixels whose colour changed by more
     than tau between two (H,W,3) uint8 frames."""
     torch = _torch()
@@ -598,14 +591,9 @@ def motion_mask(rgb, rgb_prev, tau: float, k: int, out=None, ws=None):
     dev = rgb.device
     if out is None:
         out = torch.empty((h, w), dtype=torch.uint8, device=dev)
-    if ws is None:
-        ws = torch.empty(max(motion_mask_ws_bytes(h, w), 256), dtype=torch.uint8,
-                         device=dev)
     _need(out, torch.uint8, (h, w), "out")
-    _need(ws, torch.uint8, None, "ws")
     _check(lib().jbfd_motion_mask(_ptr(rgb), _ptr(rgb_prev), h, w, float(tau),
-                                  int(k), _ptr(out), _ptr(ws), ws.numel(),
-                                  _stream(dev)))
+                                  int(k), _ptr(out), _stream(dev)))
     return out
 
 

@@ -345,16 +345,10 @@ jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_vali
                       "jbfd_backproject");
 }
 
-size_t jbfd_motion_mask_ws_bytes(int32_t H, int32_t W) {
-    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE) return 0;
-    return jbfd::motion_mask_ws_bytes(H, W);
-}
-
 jbfd_status jbfd_motion_mask(const uint8_t *rgb_hwc, const uint8_t *rgb_prev_hwc,
                              int32_t H, int32_t W, float tau, int32_t k,
-                             uint8_t *mask, void *ws, size_t ws_bytes,
-                             void *stream) {
-    if (!rgb_hwc || !rgb_prev_hwc || !mask || !ws)
+                             uint8_t *mask, void *stream) {
+    if (!rgb_hwc || !rgb_prev_hwc || !mask)
         return fail(JBFD_EINVAL, "jbfd_motion_mask: null buffer");
     jbfd_status st = check_image(H, W);
     if (st != JBFD_OK) return st;
@@ -363,13 +357,8 @@ jbfd_status jbfd_motion_mask(const uint8_t *rgb_hwc, const uint8_t *rgb_prev_hwc
                     JBFD_MOTION_MAX_K);
     if (!isfinite(tau) || tau < 0.0f)
         return fail(JBFD_EINVAL, "jbfd_motion_mask: tau must be finite and >= 0");
-    if ((uintptr_t)ws & 255)
-        return fail(JBFD_EINVAL, "jbfd_motion_mask: workspace not aligned");
-    if (ws_bytes < jbfd::motion_mask_ws_bytes(H, W))
-        return fail(JBFD_ENOSPC, "jbfd_motion_mask: workspace %zu < %zu bytes",
-                    ws_bytes, jbfd::motion_mask_ws_bytes(H, W));
     return hip_status(jbfd::launch_motion_mask(rgb_hwc, rgb_prev_hwc, H, W,
-                                               (double)tau, k, mask, ws,
+                                               (double)tau, k, mask,
                                                (hipStream_t)stream),
                       "jbfd_motion_mask");
 }

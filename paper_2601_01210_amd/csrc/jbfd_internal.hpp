@@ -135,10 +135,9 @@ hipError_t launch_backproject(const float *D, const uint8_t *M, const uint8_t *r
                               int64_t *total, void *ws, hipStream_t s);
 
 // Afterimage removal (cloud.hip, project.hip).
-size_t motion_mask_ws_bytes(int32_t H, int32_t W);
 hipError_t launch_motion_mask(const uint8_t *rgb, const uint8_t *rgb_prev,
                               int32_t H, int32_t W, double tau, int32_t k,
-                              uint8_t *mask, void *ws, hipStream_t s);
+                              uint8_t *mask, hipStream_t s);
 hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *sweep,
                                  int8_t latest, const uint8_t *motion,
                                  const Pose &P, const Intr &K, uint64_t *zbuf,

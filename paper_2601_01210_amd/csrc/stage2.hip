@@ -5,7 +5,7 @@
 //   k_pool3          one thread per 3x3 cell: valid-average depth (summed in
 //                    double in row-major order, rounded once to float), cell
 //                    validity, rounded mean colour floor((sum + n/2) / n);
-//   k_restore_merge  four pixels per thread: the original depth where the
+//   k_restore_merge  one thread per pixel: the original depth where the
 //                    pixel holds a sample, else the first pass's output of
 //                    its cell (x/3, y/3) where that is valid;
 //   k_jbf_dense<R>   the joint bilateral filter (Eq. 1-4) for inputs where
@@ -31,6 +31,11 @@
 
 namespace jbfd {
 
+// One thread per cell; grid (ceil(W1 / 256), H1). The nine pixels are read
+// from clamped addresses with every load issued before any is used; the
+// cell's in-image pixels are then taken in row-major order (adding +0.0 for
+// a pixel without a sample leaves the double sum unchanged: it starts at
+// +0.0 and so never holds -0.0).
 __global__ __launch_bounds__(256) void k_pool3(const float *__restrict__ D,
                                                const uint8_t *__restrict__ B,
                                                const uint8_t *__restrict__ rgb,
@@ -38,52 +43,64 @@ __global__ __launch_bounds__(256) void k_pool3(const float *__restrict__ D,
                                                float *__restrict__ D1,
                                                uint8_t *__restrict__ B1,
                                                uint8_t *__restrict__ rgb1) {
-    const int H1 = (H + 2) / 3, W1 = (W + 2) / 3;
-    const int64_t n = (int64_t)H1 * W1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += stride) {
-        const int cy = (int)(q / W1), cx = (int)(q - (int64_t)cy * W1);
-        double sum = 0.0;
-        int n_valid = 0, n_pix = 0;
-        int c0 = 0, c1 = 0, c2 = 0;
-        for (int y = 3 * cy; y < 3 * cy + 3 && y < H; ++y) {
-            for (int x = 3 * cx; x < 3 * cx + 3 && x < W; ++x) {
-                const int64_t p = (int64_t)y * W + x;
-                ++n_pix;
-                c0 += rgb[3 * p];
-                c1 += rgb[3 * p + 1];
-                c2 += rgb[3 * p + 2];
-                if (B[p]) {
-                    sum = sum + (double)D[p];
-                    ++n_valid;
-                }
-            }
+    const int W1 = (W + 2) / 3;
+    const int cy = blockIdx.y, cx = blockIdx.x * 256 + threadIdx.x;
+    if (cx >= W1) return;
+    float d[9];
+    uint8_t v[9], c[9][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+        const int64_t row = (int64_t)min(3 * cy + dy, H - 1) * W;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int64_t p = row + min(3 * cx + dx, W - 1);
+            d[3 * dy + dx] = D[p];
+            v[3 * dy + dx] = B[p];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) c[3 * dy + dx][ch] = rgb[3 * p + ch];
         }
-        D1[q] = n_valid ? (float)(sum / (double)n_valid) : 0.0f;
-        B1[q] = (uint8_t)(n_valid > 0);
-        rgb1[3 * q] = (uint8_t)((c0 + n_pix / 2) / n_pix);
-        rgb1[3 * q + 1] = (uint8_t)((c1 + n_pix / 2) / n_pix);
-        rgb1[3 * q + 2] = (uint8_t)((c2 + n_pix / 2) / n_pix);
     }
+    double sum = 0.0;
+    int n_valid = 0, n_pix = 0;
+    int c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int e = 3 * dy + dx;
+            const bool in = 3 * cy + dy < H && 3 * cx + dx < W;
+            const bool use = in && v[e] != 0;
+            n_pix += in;
+            c0 += in ? c[e][0] : 0;
+            c1 += in ? c[e][1] : 0;
+            c2 += in ? c[e][2] : 0;
+            sum = sum + (use ? (double)d[e] : 0.0);
+            n_valid += use;
+        }
+    }
+    const int64_t q = (int64_t)cy * W1 + cx;
+    D1[q] = n_valid ? (float)(sum / (double)n_valid) : 0.0f;
+    B1[q] = (uint8_t)(n_valid > 0);
+    rgb1[3 * q] = (uint8_t)((c0 + n_pix / 2) / n_pix);
+    rgb1[3 * q + 1] = (uint8_t)((c1 + n_pix / 2) / n_pix);
+    rgb1[3 * q + 2] = (uint8_t)((c2 + n_pix / 2) / n_pix);
 }
 
+// One thread per pixel; grid (ceil(W / 256), H).
 __global__ __launch_bounds__(256) void k_restore_merge(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const float *__restrict__ O1, const uint8_t *__restrict__ M1, int H, int W,
     float *__restrict__ D2, uint8_t *__restrict__ B2) {
     const int W1 = (W + 2) / 3;
-    const int64_t n = (int64_t)H * W;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += stride) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        const int64_t q = (int64_t)(y / 3) * W1 + x / 3;
-        const bool own = B[p] != 0;
-        const bool up = M1[q] != 0;
-        D2[p] = own ? D[p] : (up ? O1[q] : 0.0f);
-        B2[p] = (uint8_t)(own || up);
-    }
+    const int y = blockIdx.y, x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= W) return;
+    const int64_t p = (int64_t)y * W + x;
+    const int64_t q = (int64_t)(y / 3) * W1 + x / 3;
+    const uint8_t own_v = B[p], up_v = M1[q];
+    const float d = D[p], o = O1[q];
+    const bool own = own_v != 0, up = up_v != 0;
+    D2[p] = own ? d : (up ? o : 0.0f);
+    B2[p] = (uint8_t)(own || up);
 }
 
 // Filter of one 16x16 tile with one thread per pixel (see the file comment).
@@ -94,29 +111,48 @@ __global__ __launch_bounds__(256) void k_jbf_dense(
     int tiles_x, int n_tiles, int n_pad, float *__restrict__ out,
     uint8_t *__restrict__ mask) {
     constexpr int E = kTile + 2 * R;          // tile edge with halo
-    __shared__ uint4 tile[E * E];
+    __shared__ uint4 tile[E * E + 1];
     const int t = xcd_tile(blockIdx.x, n_pad);
     if (t >= n_tiles) return;                 // whole workgroup leaves together
     const int ty0 = (t / tiles_x) * kTile, tx0 = (t % tiles_x) * kTile;
 
     // stage the tile and its halo: invalid and out-of-image pixels get a
-    // zero depth and a zero valid flag
-    for (int e = threadIdx.x; e < E * E; e += 256) {
+    // zero depth and a zero valid flag. Every element's loads come from a
+    // clamped address and are issued before any is used; elements past the
+    // tile store into one spare record.
+    constexpr int NIT = (E * E + 255) / 256;
+    uint8_t cr[NIT][3], cv[NIT];
+    float cd[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = min((int)threadIdx.x + 256 * it, E * E - 1);
+        const int ly = e / E, lx = e - ly * E;
+        const int y = min(max(ty0 - R + ly, 0), H - 1);
+        const int x = min(max(tx0 - R + lx, 0), W - 1);
+        const int64_t p = (int64_t)y * W + x;
+        cr[it][0] = rgb[3 * p];
+        cr[it][1] = rgb[3 * p + 1];
+        cr[it][2] = rgb[3 * p + 2];
+        cv[it] = B[p];
+        cd[it] = D[p];
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = (int)threadIdx.x + 256 * it;
         const int ly = e / E, lx = e - ly * E;
         const int y = ty0 - R + ly, x = tx0 - R + lx;
-        uint4 rec = make_uint4(0u, 0u, 0u, 0u);
-        if (y >= 0 && y < H && x >= 0 && x < W) {
-            const int64_t p = (int64_t)y * W + x;
-            const uint8_t *c = rgb + 3 * p;
-            uint32_t rg, b0;
-            float nq2h;
-            colour_fields((uint32_t)c[0] | ((uint32_t)c[1] << 8), c[2], rg, b0, nq2h);
-            const bool v = B[p] != 0;
-            // valid flag = f16 1.0 in the upper half of the (b, 0) word
-            rec = make_uint4(rg, b0 | (v ? 0x3C000000u : 0u),
-                             __float_as_uint(v ? D[p] : 0.0f), __float_as_uint(nq2h));
-        }
-        tile[e] = rec;
+        const bool in = e < E * E && y >= 0 && y < H && x >= 0 && x < W;
+        uint32_t rg, b0;
+        float nq2h;
+        colour_fields((uint32_t)cr[it][0] | ((uint32_t)cr[it][1] << 8), cr[it][2],
+                      rg, b0, nq2h);
+        const bool v = in && cv[it] != 0;
+        // valid flag = f16 1.0 in the upper half of the (b, 0) word
+        const uint4 rec = in ? make_uint4(rg, b0 | (v ? 0x3C000000u : 0u),
+                                          __float_as_uint(v ? cd[it] : 0.0f),
+                                          __float_as_uint(nq2h))
+                             : make_uint4(0u, 0u, 0u, 0u);
+        tile[e < E * E ? e : E * E] = rec;
     }
     __syncthreads();
 
@@ -174,18 +210,11 @@ __global__ __launch_bounds__(256) void k_jbf_dense(
     mask[p] = (uint8_t)ok;
 }
 
-static int blocks_for(int64_t work, int per_block) {
-    int64_t b = (work + per_block - 1) / per_block;
-    if (b < 1) b = 1;
-    if (b > 65536) b = 65536;
-    return (int)b;
-}
-
 hipError_t launch_pool3(const float *D, const uint8_t *B, const uint8_t *rgb,
                         int32_t H, int32_t W, float *D1, uint8_t *B1,
                         uint8_t *rgb1, hipStream_t s) {
-    const int64_t cells = (int64_t)((H + 2) / 3) * ((W + 2) / 3);
-    k_pool3<<<blocks_for(cells, 256), 256, 0, s>>>(D, B, rgb, H, W, D1, B1, rgb1);
+    const dim3 grid(((W + 2) / 3 + 255) / 256, (H + 2) / 3);
+    k_pool3<<<grid, 256, 0, s>>>(D, B, rgb, H, W, D1, B1, rgb1);
     return hipGetLastError();
 }
 
@@ -193,8 +222,8 @@ hipError_t launch_restore_merge(const float *D, const uint8_t *B,
                                 const float *O1, const uint8_t *M1, int32_t H,
                                 int32_t W, float *D2, uint8_t *B2,
                                 hipStream_t s) {
-    k_restore_merge<<<blocks_for((int64_t)H * W, 256), 256, 0, s>>>(D, B, O1, M1,
-                                                                   H, W, D2, B2);
+    const dim3 grid((W + 255) / 256, H);
+    k_restore_merge<<<grid, 256, 0, s>>>(D, B, O1, M1, H, W, D2, B2);
     return hipGetLastError();
 }
 

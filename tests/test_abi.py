@@ -276,19 +276,17 @@ def test_occlusion_and_backproject_reject_bad_arguments(L):
 
 
 def test_afterimage_entry_points_reject_bad_arguments(L):
-    from paper_2601_01210_amd.binding import JBFD_EINVAL, JBFD_ENOSPC
-    fake, ws = C.c_void_p(0x1000), C.c_void_p(0x10000)
-    n = L.jbfd_motion_mask_ws_bytes(6, 8)
-    assert n >= 2 * 48 and L.jbfd_motion_mask_ws_bytes(0, 8) == 0
-    mm = lambda tau, k, w_, nb: L.jbfd_motion_mask(fake, fake, 6, 8, tau, k, fake,
-                                                   w_, nb, None)
-    assert mm(30.0, 2, ws, n - 1) == JBFD_ENOSPC
-    assert mm(30.0, -1, ws, n) == JBFD_EINVAL
-    assert mm(30.0, 17, ws, n) == JBFD_EINVAL
-    assert mm(-1.0, 2, ws, n) == JBFD_EINVAL
-    assert mm(float("nan"), 2, ws, n) == JBFD_EINVAL
-    assert mm(30.0, 2, C.c_void_p(0x10004), n) == JBFD_EINVAL
-    assert mm(30.0, 2, None, n) == JBFD_EINVAL
+    from paper_2601_01210_amd.binding import JBFD_EINVAL
+    fake = C.c_void_p(0x1000)
+    mm = lambda tau, k, out: L.jbfd_motion_mask(fake, fake, 6, 8, tau, k, out,
+                                                None)
+    assert mm(30.0, -1, fake) == JBFD_EINVAL
+    assert mm(30.0, 17, fake) == JBFD_EINVAL
+    assert mm(-1.0, 2, fake) == JBFD_EINVAL
+    assert mm(float("nan"), 2, fake) == JBFD_EINVAL
+    assert mm(float("inf"), 2, fake) == JBFD_EINVAL
+    assert mm(30.0, 2, None) == JBFD_EINVAL
+    assert L.jbfd_motion_mask(fake, fake, 0, 8, 30.0, 2, fake, None) == JBFD_EINVAL
     pose = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
     K = _K()
     pm = lambda pts, n_, sw, mo: L.jbfd_project_motion(pts, n_, sw, 0, mo, pose,

@@ -36,17 +36,22 @@ def _pair(rng, h, w, frac):
     return a, b
 
 
-MASK_CASES = [(40, 57, 0, 50.0), (40, 57, 1, 50.0), (64, 90, 2, 60.0),
-              (33, 31, 5, 40.0), (70, 70, 16, 30.0), (1, 1, 3, 10.0),
-              (1, 77, 2, 10.0), (55, 1, 2, 10.0), (20, 20, 2, 0.0)]
+# h, w, closing size k, tau, fraction of changed pixels; the workgroup
+# tile is 64 - 4k wide for k <= 8 and 128 - 4k wide above, 32 rows tall
+MASK_CASES = [(40, 57, 0, 50.0, 0.12), (40, 57, 1, 50.0, 0.12),
+              (64, 90, 2, 60.0, 0.12), (33, 31, 5, 40.0, 0.02),
+              (100, 140, 8, 40.0, 0.002), (100, 150, 9, 40.0, 0.002),
+              (70, 70, 16, 30.0, 0.12), (130, 300, 16, 30.0, 0.001),
+              (1, 1, 3, 10.0, 0.5), (1, 77, 2, 10.0, 0.12),
+              (55, 1, 2, 10.0, 0.12), (20, 20, 2, 0.0, 0.12)]
 
 
-@pytest.mark.parametrize("h,w,k,tau", MASK_CASES,
+@pytest.mark.parametrize("h,w,k,tau,frac", MASK_CASES,
                          ids=[f"{c[0]}x{c[1]}k{c[2]}" for c in MASK_CASES])
-def test_motion_mask_bit_exact(tdev, h, w, k, tau):
+def test_motion_mask_bit_exact(tdev, h, w, k, tau, frac):
     torch, dev = tdev
     from paper_2601_01210_amd import motion_mask
-    a, b = _pair(np.random.default_rng(h * 31 + k), h, w, 0.12)
+    a, b = _pair(np.random.default_rng(h * 31 + k), h, w, frac)
     got = motion_mask(_dev(torch, dev, a), _dev(torch, dev, b), tau, k)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(got.cpu().numpy(), oracle.motion_mask(a, b, tau, k))

@@ -26,7 +26,10 @@ def _dev(torch, dev, a):
                                             (70, 90, 0.1, 3, 0.1),
                                             (33, 17, 0.6, 8, 0.05),
                                             (1, 40, 0.5, 2, 0.2),
-                                            (40, 40, 1.0, 0, 0.1)])
+                                            (40, 40, 1.0, 0, 0.1),
+                                            (100, 150, 0.2, 8, 0.05),
+                                            (17, 130, 0.3, 5, 0.1),
+                                            (50, 1, 0.7, 3, 0.1)])
 def test_remove_occluded_bit_exact(tdev, h, w, dens, k, tau):
     torch, dev = tdev
     from paper_2601_01210_amd import remove_occluded
@@ -76,8 +79,15 @@ def test_backproject_ragged_and_empty(tdev):
     torch, dev = tdev
     from paper_2601_01210_amd import backproject
     rng = np.random.default_rng(9)
-    for h, w, dens in [(37, 29, 0.5), (5, 3, 1.0), (8, 8, 0.0)]:
-        dense = rng.uniform(1, 20, (h, w)).astype(np.float32)
+    # chunks of 1024 pixels straddle rows; widths below four put several
+    # rows into one thread's four pixels
+    for h, w, dens in [(37, 29, 0.5), (5, 3, 1.0), (8, 8, 0.0), (1, 3000, 0.6),
+                       (3000, 1, 0.6), (700, 2, 0.8), (61, 67, 0.9), (2, 2, 1.0)]:
+        yy, xx = np.mgrid[0:h, 0:w]
+        # a smooth ramp (kept by the contour rule) with random jumps
+        dense = (5.0 + 0.01 * xx + 0.02 * yy).astype(np.float32)
+        jump = rng.uniform(size=(h, w)) < 0.05
+        dense[jump] += rng.uniform(1, 5, int(jump.sum())).astype(np.float32)
         mask = (rng.uniform(size=(h, w)) < dens).astype(np.uint8)
         dense[mask == 0] = 0
         rgb = rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
