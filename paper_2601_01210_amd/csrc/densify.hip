@@ -399,13 +399,19 @@ __device__ void filter_tile(const float *__restrict__ D,
     const float Mfast = -fp.kr * p2;
     float num = 0.0f, den = 0.0f, dsp = 0.0f;
     if constexpr (PREC == JBFD_FP32) {
-        auto eat = [&](float t, float g, float d, uint32_t) {
-            const float a = fmaxf(__builtin_fmaf(kr2, t, Mfast), kClampExp) + g;
+        auto stage_a = [&](float t, float g, float) {
+            return fmaxf(__builtin_fmaf(kr2, t, Mfast), kClampExp) + g;
+        };
+        auto stage_b = [&](float a, float, float d) {
             const float w = __builtin_amdgcn_exp2f(a);
             num = __builtin_fmaf(w, d, num);
             den += w;
         };
-        bw.walk<false>(
+        auto eat = [&](float t, float g, float d, uint32_t) {
+            stage_b(stage_a(t, g, d), g, d);
+        };
+        bw.walk_split(
+            stage_a, stage_b,
             [&](const float (&t)[4], const float (&g)[4], const float (&d)[4],
                 const uint32_t (&uv)[4]) {
 #pragma unroll
@@ -414,14 +420,21 @@ __device__ void filter_tile(const float *__restrict__ D,
             eat);
         dsp = den;
     } else {
-        auto eat = [&](float t, float ws, float d, uint32_t) {
-            const _Float16 e = (_Float16)__builtin_fmaf(kr2, t, Mfast);
-            const float wc = (float)__builtin_exp2f16(e);
-            num = __builtin_fmaf(wc, ws * d, num);
+        // stage_a keeps the colour exponent and ws * d
+        auto stage_a = [&](float t, float ws, float d) {
+            return make_float2(__builtin_fmaf(kr2, t, Mfast), ws * d);
+        };
+        auto stage_b = [&](float2 a, float ws, float) {
+            const float wc = (float)__builtin_exp2f16((_Float16)a.x);
+            num = __builtin_fmaf(wc, a.y, num);
             den = __builtin_fmaf(wc, ws, den);
             dsp += ws;
         };
-        bw.walk<false>(
+        auto eat = [&](float t, float ws, float d, uint32_t) {
+            stage_b(stage_a(t, ws, d), ws, d);
+        };
+        bw.walk_split(
+            stage_a, stage_b,
             [&](const float (&t)[4], const float (&g)[4], const float (&d)[4],
                 const uint32_t (&uv)[4]) {
 #pragma unroll

@@ -327,22 +327,100 @@ struct BlockWalker {
         }
     }
 
-    template <bool EXACT, class E4, class E1>
-    __device__ void walk(E4 &&eat4, E1 &&eat1) const {
-        if (la.recs != nullptr) {
-            // the range [lo, hi) of the strip list; it is used only when the
-            // whole range lies inside the workspace (else stream below)
-            const int s = bx >> 3;
-            const int *ro = la.rowoff + (int64_t)s * (H + 1);
-            const int y0 = max(by - r, 0), y1 = min(by + 8 + r, H);
-            const int lo = __builtin_amdgcn_readfirstlane(ro[y0]);
-            const int hi = __builtin_amdgcn_readfirstlane(ro[y1]);
-            if (lo >= 0 && lo <= hi && (int64_t)hi <= la.capacity) {
-                walk_list<EXACT>(lo, hi, eat4, eat1);
-                return;
+    // The first pass's list walk, with the record loads of the next group
+    // of four issued after this group's table values have arrived and before
+    // its exponentials. Table reads (LDS) and record loads (scalar) share one
+    // completion counter and scalar loads complete out of order, so a table
+    // read still pending behind a record load would wait for that load too;
+    // issued here, the loads complete while the exponentials run. stage_a
+    // (t, g, d) must use g; stage_b finishes the sample. The arithmetic is
+    // the same as walk_list's with eat = stage_b o stage_a.
+    template <class SA, class SB, class E1>
+    __device__ void walk_list_split(int lo, int hi, SA &stage_a, SB &stage_b,
+                                    E1 &eat1) const {
+        const uint32_t *__restrict__ rp = la.recs;
+        int k = lo;
+        if (k + 4 <= hi) {
+            uint32_t q[4 * kRecWords];
+            const uint32_t *src = rp + (int64_t)k * kRecWords;
+#pragma unroll
+            for (int e = 0; e < 4 * kRecWords; ++e) q[e] = src[e];
+            for (;;) {
+                float g[4], d[4];
+                decltype(stage_a(0.0f, 0.0f, 0.0f)) sa[4];
+                // the four table reads first, then the colour dots under them
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    g[u] = *reinterpret_cast<const float *>(Gb + (lc - q[u * kRecWords + 4]));
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t *qq = q + u * kRecWords;
+                    const float t =
+                        dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+                    d[u] = __uint_as_float(qq[2]);
+                    sa[u] = stage_a(t, g[u], d[u]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                // the next group (the last full group again at the end, so
+                // the address stays inside the range)
+                const int kn = k + 4;
+                const uint32_t *nsrc = rp + (int64_t)min(kn, hi - 4) * kRecWords;
+#pragma unroll
+                for (int e = 0; e < 4 * kRecWords; ++e) q[e] = nsrc[e];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) stage_b(sa[u], g[u], d[u]);
+                k = kn;
+                if (k + 4 > hi) break;
             }
         }
-        // ---- stream the block's halo from the images ----
+        for (; k < hi; ++k) {
+            const uint32_t *qq = rp + (int64_t)k * kRecWords;
+            const float t = dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+            const uint32_t off = lc - qq[4];
+            eat1(t, *reinterpret_cast<const float *>(Gb + off), __uint_as_float(qq[2]),
+                 off);
+        }
+    }
+
+    // the range [lo, hi) of this block's strip list; false when there is no
+    // list or the range does not lie inside the workspace (then stream)
+    __device__ bool list_range(int &lo, int &hi) const {
+        if (la.recs == nullptr) return false;
+        const int s = bx >> 3;
+        const int *ro = la.rowoff + (int64_t)s * (H + 1);
+        const int y0 = max(by - r, 0), y1 = min(by + 8 + r, H);
+        lo = __builtin_amdgcn_readfirstlane(ro[y0]);
+        hi = __builtin_amdgcn_readfirstlane(ro[y1]);
+        return lo >= 0 && lo <= hi && (int64_t)hi <= la.capacity;
+    }
+
+    template <bool EXACT, class E4, class E1>
+    __device__ void walk(E4 &&eat4, E1 &&eat1) const {
+        int lo, hi;
+        if (list_range(lo, hi)) {
+            walk_list<EXACT>(lo, hi, eat4, eat1);
+            return;
+        }
+        stream<EXACT>(eat4, eat1);
+    }
+
+    // first pass: the split list walk, or the stream
+    template <class SA, class SB, class E4, class E1>
+    __device__ void walk_split(SA &&stage_a, SB &&stage_b, E4 &&eat4,
+                               E1 &&eat1) const {
+        int lo, hi;
+        if (list_range(lo, hi)) {
+            walk_list_split(lo, hi, stage_a, stage_b, eat1);
+            return;
+        }
+        stream<false>(eat4, eat1);
+    }
+
+    // ---- stream the block's halo from the images ----
+    template <bool EXACT, class E4, class E1>
+    __device__ void stream(E4 &eat4, E1 &eat1) const {
         const int hx0 = max(bx - r, 0), hx1 = min(bx + 8 + r, W);
         const int hy0 = max(by - r, 0), hy1 = min(by + 8 + r, H);
         const int hw = hx1 - hx0;          // >= 1: the block holds a pixel
