@@ -14,24 +14,32 @@
 //                exact tie goes to the smaller index;
 //   k_decode     key image -> float depth (0 where empty) and 0/1 mask.
 //
+// k_project_motion is k_project for afterimage removal (Sec. 4.1): points of
+// older sweeps that land in a moving pixel are dropped before the atomic.
+//
 // Traffic per frame: 12N bytes of points, 8HW to clear, the atomics, 8HW
 // read + 5HW written by the decode.
 #include "jbfd_internal.hpp"
 
 namespace jbfd {
 
+// Eight keys per thread per step, as four 16-byte stores that are each
+// contiguous across the workgroup (2048 keys per workgroup and step).
 __global__ __launch_bounds__(256) void k_fill_keys(uint64_t *__restrict__ keys,
                                                    int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 2;
     const bool vec = (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
-         i < n; i += stride) {
-        if (vec && i + 1 < n) {
-            *reinterpret_cast<ulonglong2 *>(keys + i) =
-                make_ulonglong2(kEmptyKey, kEmptyKey);
-        } else {
-            keys[i] = kEmptyKey;
-            if (i + 1 < n) keys[i + 1] = kEmptyKey;
+    const int64_t step = (int64_t)gridDim.x * 2048;
+    for (int64_t base = (int64_t)blockIdx.x * 2048; base < n; base += step) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = base + 2 * ((int64_t)threadIdx.x + 256 * j);
+            if (vec && i + 1 < n) {
+                *reinterpret_cast<ulonglong2 *>(keys + i) =
+                    make_ulonglong2(kEmptyKey, kEmptyKey);
+            } else if (i < n) {
+                keys[i] = kEmptyKey;
+                if (i + 1 < n) keys[i + 1] = kEmptyKey;
+            }
         }
     }
 }
@@ -230,7 +238,7 @@ hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
                           const Intr &K, uint64_t *zbuf, float *depth,
                           uint8_t *valid, hipStream_t s) {
     const int64_t npix = (int64_t)K.w * K.h;
-    k_fill_keys<<<grid_for(npix, 512), 256, 0, s>>>(zbuf, npix);
+    k_fill_keys<<<grid_for(npix, 2048), 256, 0, s>>>(zbuf, npix);
     if (n > 0)
         k_project<<<grid_for(n, 256), 256, 0, s>>>(
             pts, n, pose, K, reinterpret_cast<unsigned long long *>(zbuf));
@@ -244,7 +252,7 @@ hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *swee
                                  const Pose &P, const Intr &K, uint64_t *zbuf,
                                  float *depth, uint8_t *valid, hipStream_t s) {
     const int64_t npix = (int64_t)K.w * K.h;
-    k_fill_keys<<<grid_for(npix, 512), 256, 0, s>>>(zbuf, npix);
+    k_fill_keys<<<grid_for(npix, 2048), 256, 0, s>>>(zbuf, npix);
     if (n > 0)
         k_project_motion<<<grid_for(n, 256), 256, 0, s>>>(
             pts, n, sweep, latest, motion, P, K,
