@@ -8,14 +8,14 @@
 //   k_restore_merge  one thread per pixel: the original depth where the
 //                    pixel holds a sample, else the first pass's output of
 //                    its cell (x/3, y/3) where that is valid;
-//   k_jbf_dense<R>   the joint bilateral filter (Eq. 1-4) for inputs where
+//   k_jbf_dense<R,T> the joint bilateral filter (Eq. 1-4) for inputs where
 //                    most pixels hold a sample and the radius is small: one
 //                    thread per output pixel loops over every tap of its
-//                    (2R+1)^2 window, read from a 16x16 tile plus halo staged
-//                    in LDS. After pooling and restoring, nearly every window
-//                    tap is valid, so a wave-uniform walk over sample lists
-//                    (the sparse kernel) would spend most of its lanes
-//                    outside the small windows.
+//                    (2R+1)^2 window, read from a T x T tile plus halo staged
+//                    in LDS (T = 16, or 8 on small images). After pooling and
+//                    restoring, nearly every window tap is valid, so a
+//                    wave-uniform walk over sample lists (the sparse kernel)
+//                    would spend most of its lanes outside the small windows.
 //
 // Weights of k_jbf_dense follow the sparse kernel's pass 1 exactly (same
 // exponent form and clamps: colour part max(2 kr t - kr|p|^2, -60) with
@@ -103,29 +103,31 @@ __global__ __launch_bounds__(256) void k_restore_merge(
     B2[p] = (uint8_t)(own || up);
 }
 
-// Filter of one 16x16 tile with one thread per pixel (see the file comment).
-template <int R>
-__global__ __launch_bounds__(256) void k_jbf_dense(
+// Filter of one T x T tile with one thread per pixel (see the file comment);
+// T = 16, or 8 for images too small to give every CU several 16x16 tiles.
+template <int R, int T>
+__global__ __launch_bounds__(T * T) void k_jbf_dense(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
     int tiles_x, int n_tiles, int n_pad, float *__restrict__ out,
     uint8_t *__restrict__ mask) {
-    constexpr int E = kTile + 2 * R;          // tile edge with halo
+    constexpr int E = T + 2 * R;              // tile edge with halo
+    constexpr int NT = T * T;                 // threads
     __shared__ uint4 tile[E * E + 1];
     const int t = xcd_tile(blockIdx.x, n_pad);
     if (t >= n_tiles) return;                 // whole workgroup leaves together
-    const int ty0 = (t / tiles_x) * kTile, tx0 = (t % tiles_x) * kTile;
+    const int ty0 = (t / tiles_x) * T, tx0 = (t % tiles_x) * T;
 
     // stage the tile and its halo: invalid and out-of-image pixels get a
     // zero depth and a zero valid flag. Every element's loads come from a
     // clamped address and are issued before any is used; elements past the
     // tile store into one spare record.
-    constexpr int NIT = (E * E + 255) / 256;
+    constexpr int NIT = (E * E + NT - 1) / NT;
     uint8_t cr[NIT][3], cv[NIT];
     float cd[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int e = min((int)threadIdx.x + 256 * it, E * E - 1);
+        const int e = min((int)threadIdx.x + NT * it, E * E - 1);
         const int ly = e / E, lx = e - ly * E;
         const int y = min(max(ty0 - R + ly, 0), H - 1);
         const int x = min(max(tx0 - R + lx, 0), W - 1);
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_jbf_dense(
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int e = (int)threadIdx.x + 256 * it;
+        const int e = (int)threadIdx.x + NT * it;
         const int ly = e / E, lx = e - ly * E;
         const int y = ty0 - R + ly, x = tx0 - R + lx;
         const bool in = e < E * E && y >= 0 && y < H && x >= 0 && x < W;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256) void k_jbf_dense(
     }
     __syncthreads();
 
-    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
     const int px = tx0 + lx, py = ty0 + ly;
     if (px >= W || py >= H) return;           // no barrier follows
     const uint4 me = tile[(ly + R) * E + lx + R];
@@ -231,18 +233,31 @@ hipError_t launch_densify_dense(const float *D, const uint8_t *B,
                                 const uint8_t *rgb, int32_t H, int32_t W,
                                 const FilterParams &fp, float *out,
                                 uint8_t *mask, hipStream_t s) {
-    const int tiles_x = (W + kTile - 1) / kTile;
-    const int tiles_y = (H + kTile - 1) / kTile;
+    // 16x16 tiles when there are at least eight per CU, else 8x8 tiles
+    const bool big = (int64_t)((W + 15) / 16) * ((H + 15) / 16) >= 2048;
+    const int T = big ? 16 : 8;
+    const int tiles_x = (W + T - 1) / T;
+    const int tiles_y = (H + T - 1) / T;
     const int n_tiles = tiles_x * tiles_y;
     const int n_pad = (n_tiles + 7) & ~7;
+#define JBFD_DENSE_CASE(RR)                                                    \
+    case RR:                                                                   \
+        if (big)                                                               \
+            k_jbf_dense<RR, 16><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp,     \
+                                                     tiles_x, n_tiles, n_pad,  \
+                                                     out, mask);               \
+        else                                                                   \
+            k_jbf_dense<RR, 8><<<n_pad, 64, 0, s>>>(D, B, rgb, H, W, fp,       \
+                                                   tiles_x, n_tiles, n_pad,    \
+                                                   out, mask);                 \
+        break;
     switch (fp.radius) {
-    case 0: k_jbf_dense<0><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
-    case 1: k_jbf_dense<1><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
-    case 2: k_jbf_dense<2><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
-    case 3: k_jbf_dense<3><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
-    case 4: k_jbf_dense<4><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask); break;
-    default: return hipErrorInvalidValue;
+        JBFD_DENSE_CASE(0) JBFD_DENSE_CASE(1) JBFD_DENSE_CASE(2)
+        JBFD_DENSE_CASE(3) JBFD_DENSE_CASE(4)
+    default:
+        return hipErrorInvalidValue;
     }
+#undef JBFD_DENSE_CASE
     return hipGetLastError();
 }
 

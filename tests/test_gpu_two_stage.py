@@ -73,6 +73,9 @@ DENSE_CASES = [
     (50, 66, 3, 0.9, 0.25, 0.25),       # tiny widths: exact pass
     (1, 37, 2, 0.5, 1.0, 12.0),
     (17, 1, 4, 0.5, 1.0, 12.0),
+    # images with at least 2048 16x16 tiles take the 16x16-tile kernel
+    (1000, 600, 4, 0.5, 2.0, 15.0),
+    (800, 700, 1, 0.9, 1.0, 12.0),
 ]
 
 
