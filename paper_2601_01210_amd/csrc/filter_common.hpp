@@ -514,12 +514,18 @@ struct BlockWalker {
 // floored at 2^-100 inside and 0 outside (weights = true).
 __device__ inline void build_table(float *G, int r, int ts, float ks, bool weights) {
     const int tdim = 2 * r + 15;
-    for (int uy = threadIdx.x >> 6; uy < tdim; uy += 4) {
-        const int dy = uy - r - 7;
-        for (int ux = threadIdx.x & 63; ux < tdim; ux += 64) {
-            const int dx = ux - r - 7;
-            const bool in = dx >= -r && dx <= r && dy >= -r && dy <= r;
-            const float e = -ks * (float)(dx * dx + dy * dy);
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // a lane owns a column (dx), a wave walks rows (dy uniform), so the
+    // per-entry work is one add, the exponent, its clamp and a select
+    for (int ux = lane; ux < tdim; ux += 64) {
+        const int dx = ux - r - 7;
+        const bool in_x = dx >= -r && dx <= r;
+        const int dx2 = dx * dx;
+        for (int uy = wid; uy < tdim; uy += 4) {
+            const int dy = uy - r - 7;
+            const bool in = in_x && dy >= -r && dy <= r;
+            const float e = -ks * (float)(dx2 + dy * dy);
             float g;
             if (!weights)
                 g = in ? fmaxf(e, kClampExp) : -__builtin_inff();
