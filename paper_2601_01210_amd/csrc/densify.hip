@@ -417,7 +417,7 @@ __device__ void filter_tile(const float *__restrict__ D,
 #pragma unroll
                 for (int u = 0; u < 4; ++u) eat(t[u], g[u], d[u], uv[u]);
             },
-            eat);
+            eat, -__builtin_inff());
         dsp = den;
     } else {
         // stage_a keeps the colour exponent and ws * d
@@ -440,7 +440,7 @@ __device__ void filter_tile(const float *__restrict__ D,
 #pragma unroll
                 for (int u = 0; u < 4; ++u) eat(t[u], g[u], d[u], uv[u]);
             },
-            eat);
+            eat, 0.0f);
     }
 
     // Pass 2, only for lanes whose heaviest weight is below about 2^-16

@@ -334,10 +334,11 @@ struct BlockWalker {
     // read still pending behind a record load would wait for that load too;
     // issued here, the loads complete while the exponentials run. stage_a
     // (t, g, d) must use g; stage_b finishes the sample. The arithmetic is
-    // the same as walk_list's with eat = stage_b o stage_a.
+    // the same as walk_list's with eat = stage_b o stage_a. g_none is the
+    // table value of weight zero (-inf for exponents, 0 for weights).
     template <class SA, class SB, class E1>
     __device__ void walk_list_split(int lo, int hi, SA &stage_a, SB &stage_b,
-                                    E1 &eat1) const {
+                                    E1 &eat1, float g_none) const {
         const uint32_t *__restrict__ rp = la.recs;
         int k = lo;
         if (k + 4 <= hi) {
@@ -374,7 +375,27 @@ struct BlockWalker {
                 k = kn;
                 if (k + 4 > hi) break;
             }
+            // the last 1-3 samples: q already holds records [hi-4, hi) (the
+            // loads above); the first `skip` of them were consumed, and get
+            // the neutral table value g_none (weight 0: num and den are
+            // left exactly as they are)
+            if (k < hi) {
+                const int skip = k - (hi - 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t *qq = q + u * kRecWords;
+                    const float t =
+                        dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+                    const float gt =
+                        *reinterpret_cast<const float *>(Gb + (lc - qq[4]));
+                    const float g = u < skip ? g_none : gt;
+                    const float d = __uint_as_float(qq[2]);
+                    stage_b(stage_a(t, g, d), g, d);
+                }
+                k = hi;
+            }
         }
+        // lists of fewer than four samples
         for (; k < hi; ++k) {
             const uint32_t *qq = rp + (int64_t)k * kRecWords;
             const float t = dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
@@ -408,11 +429,11 @@ struct BlockWalker {
 
     // first pass: the split list walk, or the stream
     template <class SA, class SB, class E4, class E1>
-    __device__ void walk_split(SA &&stage_a, SB &&stage_b, E4 &&eat4,
-                               E1 &&eat1) const {
+    __device__ void walk_split(SA &&stage_a, SB &&stage_b, E4 &&eat4, E1 &&eat1,
+                               float g_none) const {
         int lo, hi;
         if (list_range(lo, hi)) {
-            walk_list_split(lo, hi, stage_a, stage_b, eat1);
+            walk_list_split(lo, hi, stage_a, stage_b, eat1, g_none);
             return;
         }
         stream<false>(eat4, eat1);
