@@ -350,10 +350,6 @@ __device__ void filter_tile(const float *__restrict__ D,
                             FilterShared<RMAX> &sh) {
     const int r = fp.radius;
     const int ts = table_stride(r);
-    // spatial table: clamped exponents (FP32) or weights (FP16 range)
-    build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
-    __syncthreads();
-
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int lane = threadIdx.x & 63;
     const int bx = tx * kTile + (wid & 1) * 8;
@@ -361,16 +357,20 @@ __device__ void filter_tile(const float *__restrict__ D,
     const int i = lane & 7, j = lane >> 3;
     const int px = bx + i, py = by + j;
     const bool inside = px < W && py < H;
+    // this lane's colour, from a clamped address (lanes outside the image
+    // take an edge pixel's and write nothing), loaded before the table build
+    // so that it lands under it
+    const uint8_t *c = rgb + 3 * ((int64_t)min(py, H - 1) * W + min(px, W - 1));
+    const uint8_t c0 = c[0], c1 = c[1], c2 = c[2];
+    // spatial table: clamped exponents (FP32) or weights (FP16 range)
+    build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
+    __syncthreads();
     if (bx >= W || by >= H) return;  // block of a partial tile: no outputs
 
-    float p2 = 0.0f;
-    uint32_t prg = 0, pb0 = 0;
-    if (inside) {
-        const uint8_t *c = rgb + 3 * ((int64_t)py * W + px);
-        float nh;
-        colour_fields((uint32_t)c[0] | ((uint32_t)c[1] << 8), c[2], prg, pb0, nh);
-        p2 = -2.0f * nh;
-    }
+    uint32_t prg, pb0;
+    float nh;
+    colour_fields((uint32_t)c0 | ((uint32_t)c1 << 8), c2, prg, pb0, nh);
+    const float p2 = -2.0f * nh;
     // lane constant for the table index: (i + 2r + 7, py + r + 7); a sample
     // record holds (x - (bx - r), y), so one packed subtract gives
     // (dx + r + 7, dy + r + 7) in [0, 2r+14]^2
@@ -447,8 +447,8 @@ __device__ void filter_tile(const float *__restrict__ D,
     // (clamping or precision could matter there): the exact running shift
     // of consume4/consume1 over the same samples, with exact, unclamped
     // spatial exponents.
-    const bool weak =
-        dsp > 0.0f && den < (PREC == JBFD_FP32 ? kWeakBelow : kWeakBelowF16);
+    const bool weak = inside && dsp > 0.0f &&
+                      den < (PREC == JBFD_FP32 ? kWeakBelow : kWeakBelowF16);
     float M = Mfast;
     if (__builtin_amdgcn_ballot_w64(weak) != 0) {
         float M2 = kShiftInit - fp.kr * p2, num2 = 0.0f, den2 = 0.0f;
