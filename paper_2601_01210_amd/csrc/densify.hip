@@ -347,7 +347,7 @@ __device__ void filter_tile(const float *__restrict__ D,
                             const FilterParams &fp, const ListArgs &la, int tx,
                             int ty, float *__restrict__ out,
                             uint8_t *__restrict__ mask, float2 *__restrict__ aux,
-                            FilterShared<RMAX> &sh) {
+                            FilterShared<RMAX> &sh, bool build = true) {
     const int r = fp.radius;
     const int ts = table_stride(r);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -362,9 +362,12 @@ __device__ void filter_tile(const float *__restrict__ D,
     // so that it lands under it
     const uint8_t *c = rgb + 3 * ((int64_t)min(py, H - 1) * W + min(px, W - 1));
     const uint8_t c0 = c[0], c1 = c[1], c2 = c[2];
-    // spatial table: clamped exponents (FP32) or weights (FP16 range)
-    build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
-    __syncthreads();
+    // spatial table: clamped exponents (FP32) or weights (FP16 range); a
+    // caller whose previous tile had the same radius and sigma_s keeps it
+    if (build) {
+        build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
+        __syncthreads();
+    }
     if (bx >= W || by >= H) return;  // block of a partial tile: no outputs
 
     uint32_t prg, pb0;
@@ -562,15 +565,22 @@ __global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restr
     const int n_views = hdr->n_views;
     const int total = hdr->total_tiles;
     const ListArgs none{nullptr, nullptr, 0};
+    // the spatial table depends on the radius and sigma_s only: it is
+    // rebuilt when a tile's view differs in either from the previous tile's
+    int cur_r = -1;
+    float cur_ks = 0.0f;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int lo = batch_view_of<&BatchView::tile_off>(views, n_views, t);
         const BatchView &v = views[lo];
         const int local = t - v.tile_off;
         const int ty = local / v.tiles_x, tx = local - ty * v.tiles_x;
         const FilterParams fp{v.radius, v.kr, v.ks};
+        const bool rebuild = fp.radius != cur_r || fp.ks != cur_ks;  // uniform
+        if (rebuild && cur_r >= 0) __syncthreads();  // old table no longer read
         filter_tile<RMAX, PREC>(v.sd, v.sv, v.rgb, v.H, v.W, fp, none, tx, ty,
-                                v.out, v.mask, nullptr, sh);
-        __syncthreads();   // the next tile rebuilds the table
+                                v.out, v.mask, nullptr, sh, rebuild);
+        cur_r = fp.radius;
+        cur_ks = fp.ks;
     }
 }
 
