@@ -18,7 +18,16 @@
  *   4. jbfd_batch_run - projection + filter for many viewpoints of mixed
  *                      size in one fixed-grid launch sequence that covers
  *                      every view (Sec. 2 processes each viewpoint
- *                      independently).
+ *                      independently);
+ *   5. jbfd_densify_two_stage (with jbfd_pool3, jbfd_restore_merge) - the
+ *                      two-stage filter of Sec. 5: a pass at a third of the
+ *                      resolution, then a small-radius pass at full size;
+ *   6. jbfd_motion_mask, jbfd_project_motion - afterimage removal (Sec. 4.1):
+ *                      older sweeps' points are dropped where the RGB frame
+ *                      changed;
+ *   7. jbfd_remove_occluded - occluded-point removal (Sec. 4.1);
+ *   8. jbfd_backproject - contour removal and back-projection of the dense
+ *                      depth to a coloured world point cloud (Sec. 5, Sec. 2).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
