@@ -312,10 +312,9 @@ __global__ __launch_bounds__(256) void k_motion_mask(const uint8_t *__restrict__
                                                      uint8_t *__restrict__ mask) {
     constexpr int TW = motion_tile_w(k);
     constexpr int RW = TW + 4 * k, RH = kMotionRows + 4 * k;
-    __shared__ uint8_t A[RH * RW];
-    __shared__ uint8_t Bf[RH * RW];
+    __shared__ __align__(4) uint8_t A[RH * RW];
+    __shared__ __align__(4) uint8_t Bf[RH * RW];
     const int x0 = blockIdx.x * TW - 2 * k, y0 = blockIdx.y * kMotionRows - 2 * k;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     constexpr int lw = RW == 64 ? 6 : 7;
     constexpr int n_el = RH * RW;
     // raw bits, kBatch elements per thread at a time with all their loads
@@ -351,38 +350,81 @@ __global__ __launch_bounds__(256) void k_motion_mask(const uint8_t *__restrict__
         }
     }
     __syncthreads();
-    for (int j = ty; j < RH; j += 4)                  // dilate along rows
-        for (int i = k + tx; i < RW - k; i += 64) {
-            uint8_t r = 0;
-            for (int d = -k; d <= k; ++d) r |= A[j * RW + i + d];
-            Bf[j * RW + i] = r;
+    // The closing on 32-bit words of four 0/1 bytes: OR / AND of bytes is
+    // OR / AND of words, a row shift by d bytes is one alignbyte of two
+    // neighbouring words, and a column step is a word read RW/4 words away.
+    // Words at the region's edges read clamped neighbours; the bytes that
+    // makes wrong lie outside the columns every later pass reads.
+    constexpr int NW = RW / 4;                // words per row
+    constexpr int Q = (k + 3) / 4;            // neighbour words a shift reaches
+    const uint32_t *A4 = reinterpret_cast<const uint32_t *>(A);
+    const uint32_t *B4 = reinterpret_cast<const uint32_t *>(Bf);
+    uint32_t *A4w = reinterpret_cast<uint32_t *>(A);
+    uint32_t *B4w = reinterpret_cast<uint32_t *>(Bf);
+    // OR (dilate) or AND (erode) of the row shifts -k..k of word g of row j
+    auto row_pass = [&](const uint32_t *src, int j, int g, bool dilate) {
+        uint32_t w[2 * Q + 2];
+#pragma unroll
+        for (int m = 0; m < 2 * Q + 2; ++m)
+            w[m] = src[j * NW + min(max(g - Q + m, 0), NW - 1)];
+        uint32_t r = dilate ? 0u : ~0u;
+#pragma unroll
+        for (int d = -k; d <= k; ++d) {
+            // bytes 4g + d .. 4g + d + 3
+            const int m = (d + 4 * Q) >> 2, sh = (d + 4 * Q) & 3;
+            const uint32_t v = sh == 0 ? w[m]
+                                       : __builtin_amdgcn_alignbyte(w[m + 1], w[m], sh);
+            r = dilate ? (r | v) : (r & v);
         }
+        return r;
+    };
+    constexpr int ROWS_IT = (RH + 256 / NW - 1) / (256 / NW);
+    const int wg = threadIdx.x % NW, wr = threadIdx.x / NW;   // word, row slot
+    constexpr int RSTEP = 256 / NW;
+#pragma unroll
+    for (int it = 0; it < ROWS_IT; ++it) {                 // dilate along rows
+        const int j = wr + RSTEP * it;
+        if (j < RH) B4w[j * NW + wg] = row_pass(A4, j, wg, true);
+    }
     __syncthreads();
-    for (int j = k + ty; j < RH - k; j += 4)          // dilate along columns
-        for (int i = k + tx; i < RW - k; i += 64) {
-            uint8_t r = 0;
-            for (int d = -k; d <= k; ++d) r |= Bf[(j + d) * RW + i];
-            const int y = y0 + j, x = x0 + i;
-            const bool in = y >= 0 && y < H && x >= 0 && x < W;
-            A[j * RW + i] = in ? r : (uint8_t)1;
+    const int gx = x0 + 4 * wg;              // image column of the word's byte 0
+    uint32_t outside_x = 0;                  // bytes of the word outside the image
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        outside_x |= (gx + b < 0 || gx + b >= W) ? (0xFFu << (8 * b)) : 0u;
+#pragma unroll
+    for (int it = 0; it < ROWS_IT; ++it) {                 // dilate along columns
+        const int j = wr + RSTEP * it;
+        if (j >= k && j < RH - k) {
+            uint32_t r = 0;
+#pragma unroll
+            for (int d = -k; d <= k; ++d) r |= B4[(j + d) * NW + wg];
+            const int y = y0 + j;
+            const uint32_t out = (y < 0 || y >= H) ? ~0u : outside_x;
+            A4w[j * NW + wg] = r | (out & 0x01010101u);
         }
+    }
     __syncthreads();
-    for (int j = k + ty; j < RH - k; j += 4)          // erode along rows
-        for (int i = 2 * k + tx; i < RW - 2 * k; i += 64) {
-            uint8_t r = 1;
-            for (int d = -k; d <= k; ++d) r &= A[j * RW + i + d];
-            Bf[j * RW + i] = r;
-        }
+#pragma unroll
+    for (int it = 0; it < ROWS_IT; ++it) {                 // erode along rows
+        const int j = wr + RSTEP * it;
+        if (j >= k && j < RH - k) B4w[j * NW + wg] = row_pass(A4, j, wg, false);
+    }
     __syncthreads();
-    for (int j = 2 * k + ty; j < RH - 2 * k; j += 4) {  // erode along columns
+#pragma unroll
+    for (int it = 0; it < ROWS_IT; ++it) {                 // erode along columns
+        const int j = wr + RSTEP * it;
         const int y = y0 + j;
-        if (y >= H) break;
-        for (int i = 2 * k + tx; i < RW - 2 * k; i += 64) {
-            const int x = x0 + i;
-            if (x >= W) break;
-            uint8_t r = 1;
-            for (int d = -k; d <= k; ++d) r &= Bf[(j + d) * RW + i];
-            mask[(int64_t)y * W + x] = r;
+        if (j >= 2 * k && j < RH - 2 * k && y < H) {
+            uint32_t r = ~0u;
+#pragma unroll
+            for (int d = -k; d <= k; ++d) r &= B4[(j + d) * NW + wg];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = 4 * wg + b;     // column in the region
+                if (i >= 2 * k && i < RW - 2 * k && gx + b < W)
+                    mask[(int64_t)y * W + gx + b] = (uint8_t)((r >> (8 * b)) & 1u);
+            }
         }
     }
 }
