@@ -119,19 +119,19 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current source of the kernel; else None."""
+def committed_counters(kernel: str) -> dict:
+    """The committed rocprofv3 counter summary of a kernel, if it was taken
+    on the current source of the kernel; else an empty dict."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_counters.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return {}
     if rec.get("source_digest") != source_digest():
-        return None
-    return rec.get("hbm_bytes_per_launch")
+        return {}
+    return rec
 
 
 def _fit_view(seed):
@@ -686,13 +686,22 @@ def main():
     # roofline of the filter kernel (the dominant kernel)
     t_filt = float(filt_ms.mean()) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / t_filt / 1e12
-    traffic = committed_traffic("k_jbf_fwd_f32")
+    ctr = committed_counters("k_jbf_fwd_f32")
+    traffic = ctr.get("hbm_bytes_per_launch")
+    valu = ctr.get("sq_insts_valu_per_dispatch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": traffic,
                 "kernel": "k_jbf_fwd_f32", "pairs_per_launch": pairs,
-                "flops_per_pair": FLOPS_PER_PAIR}
+                "flops_per_pair": FLOPS_PER_PAIR,
+                # the binding unit's measured use: VALU wave-instructions of
+                # one launch (rocprofv3 SQ_INSTS_VALU, committed summary) x 4
+                # cycles over 1024 SIMDs at 2.4 GHz, against this run's time
+                "valu_issue_frac": (round(valu * 4 / (1024 * 2.4e9) / t_filt, 4)
+                                    if valu else None),
+                "valu_lane_instr_per_pair": (round(valu * 64 / pairs, 2)
+                                             if valu else None)}
 
     # plain device-to-device copy of known size: the measured HBM ceiling,
     # and the reference dispatch for scaling FETCH_SIZE / WRITE_SIZE
