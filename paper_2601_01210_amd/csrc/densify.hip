@@ -156,12 +156,20 @@ __global__ __launch_bounds__(256) void k_list_scatter(
 
     // (1) records of all strips before the group: the group-and-band
     // totals of groups < g (the first g*n_bands entries of grpcnt)
+    // (eight loads per thread in flight at once: one round trip for a
+    // Full-HD image's 30 x 68 entries)
     int acc = 0;
     const int n_before = g * n_bands;
-    for (int k0 = 0; k0 < n_before; k0 += 2 * 256) {
-        const int a0 = k0 + t < n_before ? grpcnt[k0 + t] : 0;
-        const int a1 = k0 + 256 + t < n_before ? grpcnt[k0 + 256 + t] : 0;
-        acc += a0 + a1;
+    for (int k0 = 0; k0 < n_before; k0 += 8 * 256) {
+        int a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + 256 * u + t;
+            a[u] = grpcnt[k < n_before ? k : 0];
+            a[u] = k < n_before ? a[u] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += a[u];
     }
     // (2) per strip of the group: total and the part in bands before ours
     //     (32 threads per strip)
@@ -169,10 +177,21 @@ __global__ __launch_bounds__(256) void k_list_scatter(
     const int sj = s_first + j;
     int tot = 0, pre = 0;
     if (sj < n_strips) {
-        for (int b = k32; b < n_bands; b += 32) {
-            const int c = bandcnt[(int64_t)sj * n_bands + b];
-            tot += c;
-            pre += b < band ? c : 0;
+        const int *bc = bandcnt + (int64_t)sj * n_bands;
+        for (int b0 = 0; b0 < n_bands; b0 += 4 * 32) {
+            int c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + 32 * u + k32;
+                c[u] = bc[b < n_bands ? b : 0];
+                c[u] = b < n_bands ? c[u] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + 32 * u + k32;
+                tot += c[u];
+                pre += b < band ? c[u] : 0;
+            }
         }
     }
 #pragma unroll
