@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define JBFD_ABI_VERSION 1
+#define JBFD_ABI_VERSION 2
 
 /* Largest filter radius: the halo of one 8x8 output block must fit the
  * per-workgroup spatial table in LDS. */
@@ -264,14 +264,18 @@ size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
  * jbfd_batch_table_bytes(n_views) bytes (pinned memory lets the copy be
  * asynchronous and captured); the caller copies it to device memory and
  * calls jbfd_batch_run() with that device pointer. jbfd_batch_run launches
- * fixed-size grids (clear, project, decode, filter) that read every size
+ * fixed-size grids (clear, project, decode, with JBFD_BATCH_LISTS list
+ * count and list scatter, filter) that read every size
  * from the table, so the launches can be captured once into a HIP graph and
  * replayed for any batch written into the same device table, as long as
  * every radius stays <= the captured max_radius.
  *
- * Per view, the work is that of jbfd_project followed by jbfd_densify
- * (without sample lists) on the same definitions; outputs are identical to
- * the single-view calls. Views must not share output or scratch buffers.
+ * Per view, the work is that of jbfd_project followed by jbfd_densify on
+ * the same definitions (with sample lists when the run has
+ * JBFD_BATCH_LISTS and the view brings a list workspace, else streaming the
+ * halo); outputs are identical to the single-view calls made the same way. Views must not share output, scratch or list buffers.
+ * A list workspace smaller than its tables (jbfd_densify_ws_bytes with no
+ * samples) is JBFD_ENOSPC; a block whose list does not fit streams.
  */
 typedef struct jbfd_view {
     const float *points;      /* n_points x 3 float32 world xyz (device) */
@@ -286,6 +290,12 @@ typedef struct jbfd_view {
     uint8_t *sparse_valid;    /* H*W scratch/output (device) */
     float *dense_depth;       /* H*W output (device) */
     uint8_t *dense_valid;     /* H*W output (device) */
+    void *list_ws;            /* NULL, or a sample-list workspace for this
+                                 view (device, 256-byte aligned, as for
+                                 jbfd_densify; jbfd_densify_ws_bytes sizes
+                                 it): the batch then builds the view's
+                                 lists and its filter walks them */
+    size_t list_ws_bytes;     /* bytes at list_ws */
 } jbfd_view;
 
 /* Bytes of the descriptor table for n_views views (0 if n_views < 1). */
@@ -299,9 +309,13 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
 
 /* Run a batch whose table (from jbfd_batch_prepare) is at d_table (device,
  * 8-byte aligned). max_radius bounds every view's radius (it selects the
- * kernel variant and the LDS size). Capturable in a HIP graph. */
+ * kernel variant and the LDS size). flags: 0, or JBFD_BATCH_LISTS to build
+ * the sample lists of the views that bring a list workspace and walk them
+ * in the filter (without it every view streams its halo, list workspace or
+ * not). Capturable in a HIP graph. */
+#define JBFD_BATCH_LISTS 1u
 jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
-                           jbfd_precision prec, void *stream);
+                           jbfd_precision prec, uint32_t flags, void *stream);
 
 /*
  * Two-stage filtering (Sec. 5: a first pass at a third of the resolution

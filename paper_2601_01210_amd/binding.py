@@ -53,7 +53,8 @@ class View(C.Structure):
                 ("sigma_s", C.c_float), ("sigma_r", C.c_float),
                 ("zbuf", C.c_void_p), ("sparse_depth", C.c_void_p),
                 ("sparse_valid", C.c_void_p), ("dense_depth", C.c_void_p),
-                ("dense_valid", C.c_void_p)]
+                ("dense_valid", C.c_void_p), ("list_ws", C.c_void_p),
+                ("list_ws_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -127,7 +128,7 @@ def lib():
         L.jbfd_batch_prepare.restype = C.c_int
         L.jbfd_batch_prepare.argtypes = [C.POINTER(View), i32, vp, sz]
         L.jbfd_batch_run.restype = C.c_int
-        L.jbfd_batch_run.argtypes = [vp, i32, C.c_int, vp]
+        L.jbfd_batch_run.argtypes = [vp, i32, C.c_int, C.c_uint32, vp]
         _lib = L
     return _lib
 
@@ -354,12 +355,27 @@ class BatchView:
     dense_depth: object = None
     dense_valid: object = None
     n_points: Optional[int] = None
+    list_ws: object = None
+    lists: bool = False
+    list_radius: Optional[int] = None
 
     def allocate(self, device=None):
-        """Allocate any output buffer that is still None."""
+        """Allocate any output buffer that is still None, and (``lists``) a
+        sample-list workspace sized for every point of the buffer at
+        ``list_radius`` (default: the view's radius); with a larger radius
+        the blocks whose lists do not fit stream their halo instead.
+
+        Without lists the batch filter streams each block's halo. At small
+        radii that is the faster choice for a batch (building the lists of
+        eight 720p/1080p views costs more than the walk saves at r = 5); at
+        large radii the list walk is much cheaper than streaming."""
         torch = _torch()
         dev = device if device is not None else self.points.device
         hw = (self.height, self.width)
+        if self.lists and self.list_ws is None:
+            r = self.radius if self.list_radius is None else self.list_radius
+            self.list_ws = densify_workspace(self.height, self.width, int(r),
+                                             max(int(self.points.shape[0]), 1), dev)
         if self.zbuf is None:
             self.zbuf = torch.empty(hw, dtype=torch.int64, device=dev)
         if self.sparse_depth is None:
@@ -403,6 +419,10 @@ class BatchView:
         v.sparse_valid = self.sparse_valid.data_ptr()
         v.dense_depth = self.dense_depth.data_ptr()
         v.dense_valid = self.dense_valid.data_ptr()
+        if self.list_ws is not None:
+            _need(self.list_ws, torch.uint8, None, "list_ws")
+            v.list_ws = self.list_ws.data_ptr()
+            v.list_ws_bytes = self.list_ws.numel()
         return v
 
 
@@ -441,11 +461,18 @@ def batch_upload(views: Sequence[BatchView], table=None, host=None):
     return table, host
 
 
-def batch_run(table, max_radius: int, precision: Precision = Precision.FP32):
-    """Enqueue jbfd_batch_run on the current stream (graph-capturable)."""
+JBFD_BATCH_LISTS = 1
+
+
+def batch_run(table, max_radius: int, precision: Precision = Precision.FP32,
+              lists: bool = False):
+    """Enqueue jbfd_batch_run on the current stream (graph-capturable).
+    ``lists``: build and walk the sample lists of the views that carry a
+    list workspace (JBFD_BATCH_LISTS); otherwise every view streams."""
     torch = _torch()
     _need(table, torch.uint8, None, "table")
     _check(lib().jbfd_batch_run(_ptr(table), int(max_radius), int(precision),
+                                JBFD_BATCH_LISTS if lists else 0,
                                 _stream(table.device)))
 
 

@@ -6,7 +6,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
-#include "jbfd_internal.hpp"
+#include "filter_common.hpp"
 
 namespace {
 
@@ -409,7 +409,7 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
     jbfd::BatchHeader *hdr = static_cast<jbfd::BatchHeader *>(host_table);
     jbfd::BatchView *out = reinterpret_cast<jbfd::BatchView *>(
         static_cast<unsigned char *>(host_table) + sizeof(jbfd::BatchHeader));
-    int64_t tiles = 0, px_chunks = 0, pt_chunks = 0;
+    int64_t tiles = 0, px_chunks = 0, pt_chunks = 0, units = 0;
     for (int32_t v = 0; v < n_views; ++v) {
         const jbfd_view &x = views[v];
         if (!x.rgb || !x.zbuf || !x.sparse_depth || !x.sparse_valid ||
@@ -455,26 +455,56 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
                      jbfd::kBatchChunk;
         b.pt_chunk_off = (int32_t)pt_chunks;
         pt_chunks += (x.n_points + jbfd::kBatchChunk - 1) / jbfd::kBatchChunk;
+        // sample lists (as jbfd_densify with a workspace)
+        const jbfd::ListLayout L = jbfd::list_layout(x.K.height, x.K.width);
+        b.recs = nullptr;
+        b.rowoff = b.bandcnt = b.grpcnt = nullptr;
+        b.capacity = 0;
+        b.n_strips = L.n_strips;
+        b.n_groups = L.n_groups;
+        b.n_bands = L.n_bands;
+        b.unit_off = (int32_t)units;
+        if (x.list_ws) {
+            if ((uintptr_t)x.list_ws & 255)
+                return fail(JBFD_EINVAL, "batch view %d: list workspace not aligned", v);
+            jbfd::ListViews lv;
+            if (!jbfd::list_views(x.list_ws, x.list_ws_bytes, L, lv))
+                return fail(JBFD_ENOSPC, "batch view %d: list workspace %zu < %zu bytes",
+                            v, x.list_ws_bytes, L.recs);
+            if (jbfd::lists_possible(x.K.height, x.K.width, x.radius)) {
+                b.recs = lv.recs;
+                b.rowoff = lv.rowoff;
+                b.bandcnt = lv.bandcnt;
+                b.grpcnt = lv.grpcnt;
+                b.capacity = lv.capacity;
+                units += (int64_t)L.n_groups * L.n_bands;
+            }
+        }
         if (tiles >= ((int64_t)1 << 31) || px_chunks >= ((int64_t)1 << 31) ||
-            pt_chunks >= ((int64_t)1 << 31))
+            pt_chunks >= ((int64_t)1 << 31) || units >= ((int64_t)1 << 31))
             return fail(JBFD_EINVAL, "batch: too many tiles or chunks");
     }
     hdr->n_views = n_views;
     hdr->total_tiles = (int32_t)tiles;
     hdr->px_chunks = (int32_t)px_chunks;
     hdr->pt_chunks = (int32_t)pt_chunks;
+    hdr->list_units = (int32_t)units;
+    hdr->pad_ = 0;
     return ok();
 }
 
 jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
-                           jbfd_precision prec, void *stream) {
+                           jbfd_precision prec, uint32_t flags, void *stream) {
     if (!d_table || ((uintptr_t)d_table & 7))
         return fail(JBFD_EINVAL, "jbfd_batch_run: null or misaligned table");
     if (max_radius < 0 || max_radius > JBFD_MAX_RADIUS)
         return fail(JBFD_EINVAL, "jbfd_batch_run: max_radius %d", max_radius);
     if (prec != JBFD_FP32 && prec != JBFD_FP16_RANGE)
         return fail(JBFD_EINVAL, "jbfd_batch_run: unknown precision %d", (int)prec);
-    return hip_status(jbfd::launch_batch(d_table, max_radius, prec,
+    if (flags & ~JBFD_BATCH_LISTS)
+        return fail(JBFD_EINVAL, "jbfd_batch_run: unknown flags 0x%x", flags);
+    return hip_status(jbfd::launch_batch(d_table, max_radius,
+                                         (flags & JBFD_BATCH_LISTS) != 0, prec,
                                          (hipStream_t)stream),
                       "jbfd_batch_run");
 }

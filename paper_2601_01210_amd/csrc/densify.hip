@@ -94,13 +94,11 @@ __device__ inline void group_row_masks(const uint8_t *__restrict__ B, int H, int
 // Records per (strip, band): workgroup (group g, band b); wave w ballots a
 // quarter of the band's rows; lanes 0..7 count the rows' samples in the
 // halo of strip 8g + lane.
-__global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ B,
-                                                    int H, int W, int r, int n_strips,
-                                                    int n_bands,
-                                                    int *__restrict__ bandcnt,
-                                                    int *__restrict__ grpcnt) {
+__device__ inline void list_count_unit(const uint8_t *__restrict__ B, int H, int W,
+                                       int r, int n_strips, int n_bands,
+                                       int *__restrict__ bandcnt,
+                                       int *__restrict__ grpcnt, int g, int band) {
     __shared__ int part[4][kGroupStrips];
-    const int g = blockIdx.x, band = blockIdx.y;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int c0 = 64 * g - r;
@@ -130,15 +128,25 @@ __global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ 
     }
 }
 
+__global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ B,
+                                                    int H, int W, int r, int n_strips,
+                                                    int n_bands,
+                                                    int *__restrict__ bandcnt,
+                                                    int *__restrict__ grpcnt) {
+    list_count_unit(B, H, W, r, n_strips, n_bands, bandcnt, grpcnt, blockIdx.x,
+                    blockIdx.y);
+}
+
 // Offsets and records of the group's strips over one band (see the file
 // comment). The absolute start of strip s is the sum of the band counts of
 // every strip before it; the start of band b within s adds the counts of
 // bands < b.
-__global__ __launch_bounds__(256) void k_list_scatter(
+__device__ inline void list_scatter_unit(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
     int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
-    int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs) {
+    int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs, int g,
+    int band) {
     __shared__ uint64_t mlo[kBandRows], mhi[kBandRows];
     __shared__ __align__(16) int start[kBandRows][kGroupStrips];   // [row][strip]
     __shared__ int rowpos[kBandRows + 1];
@@ -146,7 +154,6 @@ __global__ __launch_bounds__(256) void k_list_scatter(
 
     __shared__ int red[4];
     __shared__ int stot[kGroupStrips], spre[kGroupStrips], sbase[kGroupStrips];
-    const int g = blockIdx.x, band = blockIdx.y;
     const int t = threadIdx.x;
     const int wid = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
@@ -341,6 +348,15 @@ __global__ __launch_bounds__(256) void k_list_scatter(
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_list_scatter(
+    const float *__restrict__ D, const uint8_t *__restrict__ B,
+    const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
+    int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
+    int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs) {
+    list_scatter_unit(D, B, rgb, H, W, r, n_strips, n_bands, bandcnt, grpcnt, rowoff,
+                      capacity, recs, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,11 +595,11 @@ namespace jbfd {
 // binary search of the table's tile offsets (wave-uniform scalar loads).
 template <int RMAX, int PREC>
 __global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restrict__ hdr,
-                                                      const BatchView *__restrict__ views) {
+                                                      const BatchView *__restrict__ views,
+                                                      bool use_lists) {
     __shared__ FilterShared<RMAX> sh;
     const int n_views = hdr->n_views;
     const int total = hdr->total_tiles;
-    const ListArgs none{nullptr, nullptr, 0};
     // the spatial table depends on the radius and sigma_s only: it is
     // rebuilt when a tile's view differs in either from the previous tile's
     int cur_r = -1;
@@ -596,28 +612,69 @@ __global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restr
         const FilterParams fp{v.radius, v.kr, v.ks};
         const bool rebuild = fp.radius != cur_r || fp.ks != cur_ks;  // uniform
         if (rebuild && cur_r >= 0) __syncthreads();  // old table no longer read
-        filter_tile<RMAX, PREC>(v.sd, v.sv, v.rgb, v.H, v.W, fp, none, tx, ty,
+        // lists only when this run built them (recs null: stream)
+        const ListArgs la{use_lists ? v.recs : nullptr, v.rowoff, v.capacity};
+        filter_tile<RMAX, PREC>(v.sd, v.sv, v.rgb, v.H, v.W, fp, la, tx, ty,
                                 v.out, v.mask, nullptr, sh, rebuild);
         cur_r = fp.radius;
         cur_ks = fp.ks;
     }
 }
 
+// Sample lists of every view that has a list workspace: fixed grids walk the
+// flattened (view, strip group, row band) units; the workgroup of a unit
+// runs the single-view kernels' body for it. Both kernels exit at once when
+// the batch has no lists.
+__global__ __launch_bounds__(256) void k_batch_list_count(const BatchHeader *__restrict__ hdr,
+                                                          const BatchView *__restrict__ views) {
+    const int n_views = hdr->n_views, units = hdr->list_units;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const BatchView &v = views[batch_view_of<&BatchView::unit_off>(views, n_views, u)];
+        const int local = u - v.unit_off;
+        const int band = local / v.n_groups, g = local - band * v.n_groups;
+        list_count_unit(v.sv, v.H, v.W, v.radius, v.n_strips, v.n_bands, v.bandcnt,
+                        v.grpcnt, g, band);
+        __syncthreads();   // the next unit reuses the LDS
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_list_scatter(const BatchHeader *__restrict__ hdr,
+                                                            const BatchView *__restrict__ views) {
+    const int n_views = hdr->n_views, units = hdr->list_units;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const BatchView &v = views[batch_view_of<&BatchView::unit_off>(views, n_views, u)];
+        const int local = u - v.unit_off;
+        const int band = local / v.n_groups, g = local - band * v.n_groups;
+        list_scatter_unit(v.sd, v.sv, v.rgb, v.H, v.W, v.radius, v.n_strips,
+                          v.n_bands, v.bandcnt, v.grpcnt, v.rowoff, v.capacity,
+                          v.recs, g, band);
+        __syncthreads();   // the next unit reuses the LDS
+    }
+}
+
+hipError_t launch_batch_lists(const BatchHeader *hdr, const BatchView *views,
+                              hipStream_t s) {
+    const int grid = 2048;   // 8 workgroups per CU
+    k_batch_list_count<<<grid, 256, 0, s>>>(hdr, views);
+    k_batch_list_scatter<<<grid, 256, 0, s>>>(hdr, views);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
                                int32_t max_radius, jbfd_precision prec,
-                               hipStream_t s) {
+                               bool use_lists, hipStream_t s) {
     const int grid = 2048;   // 8 workgroups per CU
     if (max_radius <= 16) {
         if (prec == JBFD_FP32)
-            k_batch_filter<16, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views);
+            k_batch_filter<16, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views, use_lists);
         else
-            k_batch_filter<16, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr, views);
+            k_batch_filter<16, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr, views, use_lists);
     } else {
         if (prec == JBFD_FP32)
-            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views);
+            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views, use_lists);
         else
             k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr,
-                                                                                views);
+                                                                                views, use_lists);
     }
     return hipGetLastError();
 }

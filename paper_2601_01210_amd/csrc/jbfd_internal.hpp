@@ -77,6 +77,15 @@ struct BatchView {
     int32_t n_tiles;
     int32_t px_chunk_off;   // exclusive prefix of kBatchChunk-pixel chunks
     int32_t pt_chunk_off;   // exclusive prefix of kBatchChunk-point chunks
+    // sample lists in the view's workspace (recs == nullptr: the filter
+    // streams the halo); list units are (strip group, row band) pairs
+    uint32_t *recs;
+    int *rowoff;
+    int *bandcnt;
+    int *grpcnt;
+    int64_t capacity;       // records the workspace holds
+    int32_t n_strips, n_groups, n_bands;
+    int32_t unit_off;       // exclusive prefix of list units over the views
 };
 
 // Elements (pixels or points) one workgroup handles per batch chunk.
@@ -87,6 +96,8 @@ struct BatchHeader {
     int32_t total_tiles;
     int32_t px_chunks;
     int32_t pt_chunks;
+    int32_t list_units;     // list units of every view with lists
+    int32_t pad_;           // keeps the views 8-byte aligned
 };
 
 // Last view v with views[v].*field <= c (the fields are exclusive prefixes,
@@ -143,10 +154,12 @@ hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *swee
                                  const Pose &P, const Intr &K, uint64_t *zbuf,
                                  float *depth, uint8_t *valid, hipStream_t s);
 
-hipError_t launch_batch(const void *d_table, int32_t max_radius,
+hipError_t launch_batch_lists(const BatchHeader *hdr, const BatchView *views,
+                              hipStream_t s);
+hipError_t launch_batch(const void *d_table, int32_t max_radius, bool use_lists,
                         jbfd_precision prec, hipStream_t s);
 hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
                                int32_t max_radius, jbfd_precision prec,
-                               hipStream_t s);
+                               bool use_lists, hipStream_t s);
 
 }  // namespace jbfd

@@ -262,7 +262,7 @@ hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *swee
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const void *d_table, int32_t max_radius,
+hipError_t launch_batch(const void *d_table, int32_t max_radius, bool use_lists,
                         jbfd_precision prec, hipStream_t s) {
     const BatchHeader *hdr = static_cast<const BatchHeader *>(d_table);
     const BatchView *views = reinterpret_cast<const BatchView *>(
@@ -271,9 +271,13 @@ hipError_t launch_batch(const void *d_table, int32_t max_radius,
     k_batch_clear<<<grid, 256, 0, s>>>(hdr, views);
     k_batch_project<<<grid, 256, 0, s>>>(hdr, views);
     k_batch_decode<<<grid, 256, 0, s>>>(hdr, views);
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_batch_filter(hdr, views, max_radius, prec, s);
+    if (use_lists) {
+        e = launch_batch_lists(hdr, views, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_batch_filter(hdr, views, max_radius, prec, use_lists, s);
 }
 
 }  // namespace jbfd

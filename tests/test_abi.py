@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_status_strings(L):
     from paper_2601_01210_amd import binding
-    assert L.jbfd_abi_version() == 1
+    assert L.jbfd_abi_version() == 2
     for code in range(5):
         assert L.jbfd_status_string(code)
     assert L.jbfd_status_string(99) == b"unknown status"
@@ -211,11 +211,12 @@ def test_batch_prepare_rejects_bad_pose_and_size(L):
 def test_batch_run_rejects_bad_arguments(L):
     from paper_2601_01210_amd.binding import JBFD_EINVAL
     fake = C.c_void_p(0x1000)
-    assert L.jbfd_batch_run(None, 5, 0, None) == JBFD_EINVAL
-    assert L.jbfd_batch_run(C.c_void_p(0x1004), 5, 0, None) == JBFD_EINVAL
-    assert L.jbfd_batch_run(fake, 33, 0, None) == JBFD_EINVAL
-    assert L.jbfd_batch_run(fake, -1, 0, None) == JBFD_EINVAL
-    assert L.jbfd_batch_run(fake, 5, 7, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(None, 5, 0, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(C.c_void_p(0x1004), 5, 0, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, 33, 0, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, -1, 0, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, 5, 7, 0, None) == JBFD_EINVAL
+    assert L.jbfd_batch_run(fake, 5, 0, 2, None) == JBFD_EINVAL    # unknown flag
 
 
 def test_two_stage_and_dense_reject_bad_arguments(L):
@@ -299,3 +300,31 @@ def test_afterimage_entry_points_reject_bad_arguments(L):
     bad = (C.c_double * 12)(1, 0, 0, 0, 0, float("nan"), 0, 0, 0, 0, 1, 0)
     assert L.jbfd_project_motion(fake, 10, fake, 0, fake, bad, C.byref(K), fake,
                                  None, None, None) == JBFD_EINVAL
+
+
+def test_batch_prepare_checks_list_workspaces(L):
+    """A view's list workspace must be 256-byte aligned and hold at least
+    the list tables (host-side checks; nothing runs on a device)."""
+    from paper_2601_01210_amd.binding import (JBFD_EINVAL, JBFD_ENOSPC, JBFD_OK,
+                                              Intrinsics, View)
+    import numpy as np
+    fake = 0x100000
+    v = View()
+    v.points, v.n_points = fake, 10
+    v.cam_from_world = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    v.K = Intrinsics(4.0, 4.0, 4.0, 3.0, 64, 48)
+    v.rgb = v.zbuf = v.sparse_depth = v.sparse_valid = fake
+    v.dense_depth = v.dense_valid = fake
+    v.radius, v.sigma_s, v.sigma_r = 5, 3.0, 12.0
+    nb = L.jbfd_batch_table_bytes(1)
+    host = np.zeros(nb, np.uint8)
+    tables = L.jbfd_densify_ws_bytes(48, 64, 5, 0)
+    prep = lambda: L.jbfd_batch_prepare(C.byref(v), 1, host.ctypes.data, nb)
+    v.list_ws, v.list_ws_bytes = None, 0
+    assert prep() == JBFD_OK                            # no lists: streams
+    v.list_ws, v.list_ws_bytes = fake, tables
+    assert prep() == JBFD_OK
+    v.list_ws_bytes = tables - 1
+    assert prep() == JBFD_ENOSPC
+    v.list_ws, v.list_ws_bytes = fake + 4, tables
+    assert prep() == JBFD_EINVAL

@@ -67,10 +67,10 @@ def _views(torch, dev, frames, **over):
     return vs
 
 
-def _run(torch, views, precision):
+def _run(torch, views, precision, lists=False):
     from paper_2601_01210_amd import batch_run, batch_upload
     table, host = batch_upload(views)
-    batch_run(table, max(v.radius for v in views), precision)
+    batch_run(table, max(v.radius for v in views), precision, lists=lists)
     torch.cuda.synchronize()
     return table, host
 
@@ -97,7 +97,8 @@ def test_batch_fp32_matches_oracle_and_single_views(tdev, frames, refs):
         rel = np.abs(out[sel] - ref[sel]) / np.abs(ref[sel])
         assert rel.max() <= 1e-5, (k, rel.max())
         assert np.all(out[~sel] == 0)
-        # single-view calls on the same inputs give identical bits
+        # single-view calls on the same inputs (streaming the halo, as the
+        # batch views without list workspaces) give identical bits
         zs, ds, bs = project(v.points, v.pose, v.intrinsics, v.width, v.height)
         so, sm = densify(ds, bs, v.rgb, v.radius, v.sigma_s, v.sigma_r, ws=None)
         torch.cuda.synchronize()
@@ -166,6 +167,52 @@ def test_batch_mixed_filters_and_degenerate_views(tdev):
         np.testing.assert_allclose(out[m == 1], ref[m == 1], rtol=1e-5)
     assert int(views[-1].dense_valid.sum()) == 0
     assert int(views[-1].sparse_valid.sum()) == 0
+
+
+def test_batch_lists_streaming_and_overflow_agree(tdev, frames):
+    """With JBFD_BATCH_LISTS the batch builds each view's sample lists in
+    its list workspace and the filter walks them; without a workspace the
+    filter streams the halo,
+    and with a workspace too small for every record the blocks whose lists
+    do not fit stream. The masks agree bit for bit; the depths too, except
+    at lanes that take the exact pass (tiny weight sums), whose running
+    shift groups the samples differently when streaming: there they agree
+    to rounding."""
+    torch, dev = tdev
+    from paper_2601_01210_amd import Precision, densify_ws_bytes
+    sub = frames[:4]
+    with_lists = _views(torch, dev, sub, lists=True)
+    streaming = _views(torch, dev, sub)
+    small = _views(torch, dev, sub)
+    for v in small:
+        # room for a tenth of the valid pixels' records
+        n = densify_ws_bytes(v.height, v.width, v.radius, max(v.points.shape[0] // 10, 1))
+        v.list_ws = torch.empty(n, dtype=torch.uint8, device=dev)
+    for vs in (with_lists, streaming, small):
+        _run(torch, vs, Precision.FP32, lists=True)
+    from paper_2601_01210_amd import densify
+    for a, b, c in zip(with_lists, streaming, small):
+        assert a.list_ws is not None and b.list_ws is None
+        # with lists, the batch equals single-view calls with lists
+        so, sm = densify(a.sparse_depth, a.sparse_valid, a.rgb, a.radius, a.sigma_s,
+                         a.sigma_r)
+        torch.cuda.synchronize()
+        assert torch.equal(so.view(torch.int32), a.dense_depth.view(torch.int32))
+        assert torch.equal(sm, a.dense_valid)
+        for x in (b, c):
+            assert torch.equal(a.dense_valid, x.dense_valid)
+            da, dx = a.dense_depth.cpu().numpy(), x.dense_depth.cpu().numpy()
+            sel = a.dense_valid.cpu().numpy() == 1
+            rel = np.abs(da[sel] - dx[sel]) / np.abs(da[sel])
+            assert rel.max() <= 1e-6, rel.max()
+            assert (da != dx).mean() <= 1e-4, (da != dx).mean()
+    # without the flag, views that carry a list workspace stream too
+    flagless = _views(torch, dev, sub, lists=True)
+    _run(torch, flagless, Precision.FP32)
+    for b, x in zip(streaming, flagless):
+        assert torch.equal(b.dense_depth.view(torch.int32),
+                           x.dense_depth.view(torch.int32))
+        assert torch.equal(b.dense_valid, x.dense_valid)
 
 
 def test_batch_graph_replays_match_eager(tdev, frames):
