@@ -557,7 +557,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: viewpoints are independent and "
-              "this build measures the single-GPU path (--gpus 1).",
+              "the benchmark measures the single-GPU path (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 

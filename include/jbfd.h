@@ -82,7 +82,7 @@ extern "C" {
 typedef enum jbfd_status {
     JBFD_OK = 0,
     JBFD_EINVAL = 1,      /* bad argument (null pointer, size, radius, sigma) */
-    JBFD_EUNSUPPORTED = 2, /* valid request this build does not implement */
+    JBFD_EUNSUPPORTED = 2, /* valid request this library does not implement */
     JBFD_EHIP = 3,        /* HIP runtime or launch error, see jbfd_last_error */
     JBFD_ENOSPC = 4       /* caller workspace smaller than the queried size */
 } jbfd_status;

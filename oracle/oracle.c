@@ -1,7 +1,7 @@
 /*
  * FP64 CPU oracle for LiDAR depth densification (test infrastructure only).
  *
- * This file is the checker, not the product. Only the test suite, the smoke
+ * This file is test infrastructure, not the product. Only the test suite, the smoke
  * check and the benchmark's CPU-baseline leg load it. It shares no source,
  * header, table or helper with the GPU library.
  *
