@@ -17,6 +17,8 @@ constexpr float kClampExp = -60.0f;       // pass-1 floor of each exponent part
 constexpr float kWeakBelow = 1.52587890625e-05f;  // 2^-16: pass-2 threshold
 constexpr float kWeakBelowF16 = 0.00390625f;      // 2^-8: same, FP16 weights
 constexpr int kRecWords = 5;       // list record size in 32-bit words
+constexpr int NG = 4;              // records per group of the first pass's list
+                                   // walk (6 and 8 measured no faster)
 
 struct alignas(16) Rec {
     uint32_t xy;   // x - (bx - r) | y << 16
@@ -341,21 +343,21 @@ struct BlockWalker {
                                     E1 &eat1, float g_none) const {
         const uint32_t *__restrict__ rp = la.recs;
         int k = lo;
-        if (k + 4 <= hi) {
-            uint32_t q[4 * kRecWords];
+        if (k + NG <= hi) {
+            uint32_t q[NG * kRecWords];
             const uint32_t *src = rp + (int64_t)k * kRecWords;
 #pragma unroll
-            for (int e = 0; e < 4 * kRecWords; ++e) q[e] = src[e];
+            for (int e = 0; e < NG * kRecWords; ++e) q[e] = src[e];
             for (;;) {
-                float g[4], d[4];
-                decltype(stage_a(0.0f, 0.0f, 0.0f)) sa[4];
-                // the four table reads first, then the colour dots under them
+                float g[NG], d[NG];
+                decltype(stage_a(0.0f, 0.0f, 0.0f)) sa[NG];
+                // the group's table reads first, then the colour dots under them
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < NG; ++u)
                     g[u] = *reinterpret_cast<const float *>(Gb + (lc - q[u * kRecWords + 4]));
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NG; ++u) {
                     const uint32_t *qq = q + u * kRecWords;
                     const float t =
                         dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
@@ -365,24 +367,24 @@ struct BlockWalker {
                 __builtin_amdgcn_sched_barrier(0);
                 // the next group (the last full group again at the end, so
                 // the address stays inside the range)
-                const int kn = k + 4;
-                const uint32_t *nsrc = rp + (int64_t)min(kn, hi - 4) * kRecWords;
+                const int kn = k + NG;
+                const uint32_t *nsrc = rp + (int64_t)min(kn, hi - NG) * kRecWords;
 #pragma unroll
-                for (int e = 0; e < 4 * kRecWords; ++e) q[e] = nsrc[e];
+                for (int e = 0; e < NG * kRecWords; ++e) q[e] = nsrc[e];
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) stage_b(sa[u], g[u], d[u]);
+                for (int u = 0; u < NG; ++u) stage_b(sa[u], g[u], d[u]);
                 k = kn;
-                if (k + 4 > hi) break;
+                if (k + NG > hi) break;
             }
-            // the last 1-3 samples: q already holds records [hi-4, hi) (the
+            // the last 1 .. NG-1 samples: q already holds records [hi-NG, hi) (the
             // loads above); the first `skip` of them were consumed, and get
             // the neutral table value g_none (weight 0: num and den are
             // left exactly as they are)
             if (k < hi) {
-                const int skip = k - (hi - 4);
+                const int skip = k - (hi - NG);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NG; ++u) {
                     const uint32_t *qq = q + u * kRecWords;
                     const float t =
                         dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
@@ -395,7 +397,7 @@ struct BlockWalker {
                 k = hi;
             }
         }
-        // lists of fewer than four samples
+        // lists of fewer than NG samples
         for (; k < hi; ++k) {
             const uint32_t *qq = rp + (int64_t)k * kRecWords;
             const float t = dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
