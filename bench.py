@@ -111,11 +111,16 @@ def window_pairs(valid: np.ndarray, r: int) -> int:
     return int((wx.astype(np.int64) * wy).sum())
 
 
+# Sources the sparse filter kernel is compiled from: counters taken on
+# another version of any of them no longer describe it.
+FILTER_SOURCES = ("densify.hip", "filter_common.hpp", "jbfd_internal.hpp")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
-    src = os.path.join(ROOT, "paper_2601_01210_amd", "csrc", "densify.hip")
-    with open(src, "rb") as f:
-        h.update(f.read())
+    for name in FILTER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_01210_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -182,8 +182,9 @@ jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
  * dense_depth     H*W float32 output (device)
  * dense_valid     H*W uint8 output (device)
  * aux             NULL, or H*W*2 float32 output (device) saved for
- *                 jbfd_densify_backward: per pixel the log2 shift of its
- *                 weights and the shifted weight sum (FP32 precision only)
+ *                 jbfd_densify_backward: per pixel the log2 shift its
+ *                 weights were formed with and their weight sum (FP32
+ *                 precision only; the backward recomputes the same weights)
  * ws, ws_bytes    NULL/0, or a device workspace (256-byte aligned). With at
  *                 least jbfd_densify_ws_bytes(H, W, radius, n) bytes, where
  *                 n bounds the number of valid samples (the number of

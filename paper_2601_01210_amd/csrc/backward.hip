@@ -31,7 +31,7 @@ struct alignas(16) OutRec {
     uint32_t xy;   // x - (bx - r) | y << 16 of the output pixel
     uint32_t rg;   // its colour (r, g) as f16
     uint32_t b0;   // (b, 0) as f16
-    float M;       // its weight shift
+    float M;       // its weight shift (pass-1 pixels: their Pass1Exp lane constant)
 };
 
 __device__ inline double wave_sum(double v) {
@@ -46,7 +46,7 @@ template <int RMAX>
 __global__ __launch_bounds__(256) void k_jbf_bwd_sigma(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
-    int tiles_x, int n_tiles, int n_pad, const float *__restrict__ out,
+    int tiles_x, int tiles_y, const float *__restrict__ out,
     const float2 *__restrict__ aux, const float *__restrict__ gout,
     float inv_sr3, float inv_ss3, double *__restrict__ partials) {
     constexpr int kTableMax = (2 * RMAX + 15) * table_stride(RMAX);
@@ -56,15 +56,14 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_sigma(
 
     const int r = fp.radius;
     const int ts = table_stride(r);
-    const int tile = xcd_tile(blockIdx.x, n_pad);
-    if (tile >= n_tiles) return;
+    int tx, ty;
+    if (!column_tile(blockIdx.x, tiles_x, tiles_y, tx, ty)) return;
     build_table(G, r, ts, fp.ks, false);
     __syncthreads();
 
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int slot = tile * kWaves + wid;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int slot = (ty * tiles_x + tx) * kWaves + wid;
     const int bx = tx * kTile + (wid & 1) * 8;
     const int by = ty * kTile + (wid >> 1) * 8;
     const int i = lane & 7, j = lane >> 3;
@@ -106,12 +105,13 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_sigma(
     // the forward's weight of this (pixel, sample) pair
     const bool pass1 = ax.y < 0.0f;
     const float M = ax.x;
+    const Pass1Exp p1(kr2, M);
     float Ar = 0.0f, As = 0.0f;
     auto eat = [&](float t, float gtab, float d, uint32_t uv) {
         if (!active) return;
         float a;
         if (pass1)
-            a = fmaxf(__builtin_fmaf(kr2, t, M), kClampExp) + gtab;
+            a = p1(t, gtab);
         else
             a = __builtin_fmaf(kr2, t, M) + bw.exact_g(uv);
         const float w = __builtin_amdgcn_exp2f(a);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_sigma(
 template <int RMAX>
 __global__ __launch_bounds__(256) void k_jbf_bwd_depth(
     const uint8_t *__restrict__ B, const uint8_t *__restrict__ rgb, int H,
-    int W, FilterParams fp, int tiles_x, int n_tiles, int n_pad,
+    int W, FilterParams fp, int tiles_x, int tiles_y,
     const float2 *__restrict__ aux, const float *__restrict__ gout,
     float *__restrict__ grad_d) {
     constexpr int kTableMax = (2 * RMAX + 15) * table_stride(RMAX);
@@ -158,14 +158,13 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_depth(
 
     const int r = fp.radius;
     const int ts = table_stride(r);
-    const int tile = xcd_tile(blockIdx.x, n_pad);
-    if (tile >= n_tiles) return;
+    int tx, ty;
+    if (!column_tile(blockIdx.x, tiles_x, tiles_y, tx, ty)) return;
     build_table(G, r, ts, fp.ks, false);
     __syncthreads();
 
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int bx = tx * kTile + (wid & 1) * 8;
     const int by = ty * kTile + (wid >> 1) * 8;
     const int i = lane & 7, j = lane >> 3;
@@ -189,6 +188,7 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_depth(
     const uint32_t gstride = 4u | ((uint32_t)(4 * ts) << 16);
     const unsigned char *Gb = reinterpret_cast<const unsigned char *>(G);
     const float kr2 = 2.0f * fp.kr, nks = -fp.ks;
+    const float k1 = Pass1Exp(kr2, 0.0f).k;
 
     // the output pixels of the halo with a nonzero upstream gradient
     const int hx0 = max(bx - r, 0), hx1 = min(bx + 8 + r, W);
@@ -221,7 +221,8 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_depth(
             colour_fields((uint32_t)c[0] | ((uint32_t)c[1] << 8), c[2], rec.rg,
                           rec.b0, dummy);
             rec.xy = (uint32_t)(sx - (bx - r)) | ((uint32_t)sy << 16);
-            rec.M = ax.x;
+            // a pass-1 pixel's record carries its Pass1Exp lane constant
+            rec.M = ax.y < 0.0f ? Pass1Exp::lane_c(ax.x) : ax.x;
             const int pos = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             my[pos] = rec;
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(256) void k_jbf_bwd_depth(
             float a;
             if (myf[e]) {
                 const float g = *reinterpret_cast<const float *>(Gb + dot2_u16(uv, gstride, 0u));
-                a = fmaxf(__builtin_fmaf(kr2, t, o.M), kClampExp) + g;
+                a = Pass1Exp::eval(k1, o.M, t, g);
             } else {
                 const int dx = (int)(uv & 0xffffu) - r - 7, dy = (int)(uv >> 16) - r - 7;
                 const bool in = dx >= -r && dx <= r && dy >= -r && dy <= r;
@@ -275,16 +276,15 @@ __global__ __launch_bounds__(256) void k_reduce_sigma(const double *__restrict__
     }
 }
 
-static void tiles(int H, int W, int &tiles_x, int &n_tiles, int &n_pad) {
+static void tiles(int H, int W, int &tiles_x, int &tiles_y) {
     tiles_x = (W + kTile - 1) / kTile;
-    n_tiles = tiles_x * ((H + kTile - 1) / kTile);
-    n_pad = (n_tiles + 7) & ~7;
+    tiles_y = (H + kTile - 1) / kTile;
 }
 
 size_t backward_ws_bytes(int32_t H, int32_t W) {
-    int tiles_x, n_tiles, n_pad;
-    tiles(H, W, tiles_x, n_tiles, n_pad);
-    return (size_t)n_tiles * kWaves * 2 * sizeof(double);
+    int tiles_x, tiles_y;
+    tiles(H, W, tiles_x, tiles_y);
+    return (size_t)tiles_x * tiles_y * kWaves * 2 * sizeof(double);
 }
 
 hipError_t launch_densify_backward(const float *D, const uint8_t *B,
@@ -294,8 +294,9 @@ hipError_t launch_densify_backward(const float *D, const uint8_t *B,
                                    const float *aux, const float *g,
                                    float *grad_d, double *grad_sigmas,
                                    void *ws, hipStream_t s) {
-    int tiles_x, n_tiles, n_pad;
-    tiles(H, W, tiles_x, n_tiles, n_pad);
+    int tiles_x, tiles_y;
+    tiles(H, W, tiles_x, tiles_y);
+    const int n_tiles = tiles_x * tiles_y, n_wg = column_grid(tiles_x, tiles_y);
     const float inv_sr3 =
         __builtin_isinf(sigma_r) ? 0.0f : (float)(1.0 / ((double)sigma_r * sigma_r * sigma_r));
     const float inv_ss3 =
@@ -303,17 +304,17 @@ hipError_t launch_densify_backward(const float *D, const uint8_t *B,
     double *partials = static_cast<double *>(ws);
     const float2 *a2 = reinterpret_cast<const float2 *>(aux);
     if (fp.radius <= 16) {
-        k_jbf_bwd_sigma<16><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x,
-                                                 n_tiles, n_pad, out, a2, g, inv_sr3,
-                                                 inv_ss3, partials);
-        k_jbf_bwd_depth<16><<<n_pad, 256, 0, s>>>(B, rgb, H, W, fp, tiles_x, n_tiles,
-                                                 n_pad, a2, g, grad_d);
+        k_jbf_bwd_sigma<16><<<n_wg, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x,
+                                                tiles_y, out, a2, g, inv_sr3,
+                                                inv_ss3, partials);
+        k_jbf_bwd_depth<16><<<n_wg, 256, 0, s>>>(B, rgb, H, W, fp, tiles_x, tiles_y,
+                                                a2, g, grad_d);
     } else {
-        k_jbf_bwd_sigma<JBFD_MAX_RADIUS><<<n_pad, 256, 0, s>>>(
-            D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, a2, g, inv_sr3,
+        k_jbf_bwd_sigma<JBFD_MAX_RADIUS><<<n_wg, 256, 0, s>>>(
+            D, B, rgb, H, W, fp, tiles_x, tiles_y, out, a2, g, inv_sr3,
             inv_ss3, partials);
-        k_jbf_bwd_depth<JBFD_MAX_RADIUS><<<n_pad, 256, 0, s>>>(
-            B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, a2, g, grad_d);
+        k_jbf_bwd_depth<JBFD_MAX_RADIUS><<<n_wg, 256, 0, s>>>(
+            B, rgb, H, W, fp, tiles_x, tiles_y, a2, g, grad_d);
     }
     k_reduce_sigma<<<1, 256, 0, s>>>(partials, n_tiles * kWaves, grad_sigmas);
     return hipGetLastError();

@@ -43,7 +43,9 @@
 //            subtract and the window test is free;
 //   weight   w = exp2(max(2 kr t - kr|p|^2, -60) + G), kr and ks in log2
 //            units (the table is clamped at -60 too), so every in-window
-//            sample has w >= 2^-120 > 0 and den > 0 is exactly the mask.
+//            sample has w >= 2^-120 > 0 and den > 0 is exactly the mask;
+//            the clamp rides on an fma's output modifier (Pass1Exp), so
+//            a sample costs nine VALU instructions.
 // Lanes whose weight sum ends below 2^-16 (far colours: clamping or
 // rounding could matter) are recomputed in a second pass with an exact
 // running shift M: it starts at 2^23 - kr|p|^2 and drops by whole integers k
@@ -67,7 +69,7 @@ size_t densify_ws_bytes(int32_t H, int32_t W, int32_t r, int64_t max_samples) {
 // (columns outside the image read as invalid). All loads are issued before
 // the first ballot.
 template <int NROWS>
-__device__ inline void group_row_masks(const uint8_t *__restrict__ B, int H, int W,
+__device__ __forceinline__ void group_row_masks(const uint8_t *__restrict__ B, int H, int W,
                                        int c0, int y_first, uint64_t (&lo)[NROWS],
                                        uint64_t (&hi)[NROWS]) {
     const int lane = threadIdx.x & 63;
@@ -93,8 +95,10 @@ __device__ inline void group_row_masks(const uint8_t *__restrict__ B, int H, int
 
 // Records per (strip, band): workgroup (group g, band b); wave w ballots a
 // quarter of the band's rows; lanes 0..7 count the rows' samples in the
-// halo of strip 8g + lane.
-__device__ inline void list_count_unit(const uint8_t *__restrict__ B, int H, int W,
+// halo of strip 8g + lane. (The unit functions are forced inline: called out
+// of line, their uniform arguments and pointers would live in vector
+// registers and their loads would lose their scalar bases.)
+__device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, int H, int W,
                                        int r, int n_strips, int n_bands,
                                        int *__restrict__ bandcnt,
                                        int *__restrict__ grpcnt, int g, int band) {
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ 
 // comment). The absolute start of strip s is the sum of the band counts of
 // every strip before it; the start of band b within s adds the counts of
 // bands < b.
-__device__ inline void list_scatter_unit(
+__device__ __forceinline__ void list_scatter_unit(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
     int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
@@ -376,7 +380,7 @@ struct FilterShared {
 // Every thread returns normally, so callers may loop over tiles with a
 // barrier between them.
 template <int RMAX, int PREC>
-__device__ void filter_tile(const float *__restrict__ D,
+__device__ __forceinline__ void filter_tile(const float *__restrict__ D,
                             const uint8_t *__restrict__ B,
                             const uint8_t *__restrict__ rgb, int H, int W,
                             const FilterParams &fp, const ListArgs &la, int tx,
@@ -426,7 +430,8 @@ __device__ void filter_tile(const float *__restrict__ D,
     // so a = fma(2kr, t, -kr|p|^2) + G (the fma rounds once, relative to the
     // colour exponent itself; the rounded lane constant -kr|p|^2 shifts every
     // weight of the lane alike and cancels) never overflows.
-    //  FP32: the colour part is clamped at -60 and the table at -60, so an
+    //  FP32: the colour part is clamped at -60 and the table at -60 (the
+    //        colour clamp and the sum take two fmas, Pass1Exp), so an
     //        in-window sample never underflows to zero and den > 0 exactly
     //        when the window holds a sample.
     //  FP16 range weights: the colour exponent is rounded to FP16 by the
@@ -437,9 +442,8 @@ __device__ void filter_tile(const float *__restrict__ D,
     const float Mfast = -fp.kr * p2;
     float num = 0.0f, den = 0.0f, dsp = 0.0f;
     if constexpr (PREC == JBFD_FP32) {
-        auto stage_a = [&](float t, float g, float) {
-            return fmaxf(__builtin_fmaf(kr2, t, Mfast), kClampExp) + g;
-        };
+        const Pass1Exp p1(kr2, Mfast);
+        auto stage_a = [&](float t, float g, float) { return p1(t, g); };
         auto stage_b = [&](float a, float, float d) {
             const float w = __builtin_amdgcn_exp2f(a);
             num = __builtin_fmaf(w, d, num);
@@ -520,12 +524,12 @@ template <int RMAX, int PREC>
 __global__ __launch_bounds__(256) void k_jbf_fwd(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
-    int tiles_x, int n_tiles, int n_pad, ListArgs la, float *__restrict__ out,
+    int tiles_x, int tiles_y, ListArgs la, float *__restrict__ out,
     uint8_t *__restrict__ mask, float2 *__restrict__ aux) {
     __shared__ FilterShared<RMAX> sh;
-    const int tile = xcd_tile(blockIdx.x, n_pad);
-    if (tile >= n_tiles) return;  // whole workgroup leaves together
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    int tx, ty;
+    if (!column_tile(blockIdx.x, tiles_x, tiles_y, tx, ty))
+        return;  // whole workgroup leaves together
     filter_tile<RMAX, PREC>(D, B, rgb, H, W, fp, la, tx, ty, out, mask, aux, sh);
 }
 
@@ -553,8 +557,7 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                           hipStream_t s) {
     const int tiles_x = (W + kTile - 1) / kTile;
     const int tiles_y = (H + kTile - 1) / kTile;
-    const int n_tiles = tiles_x * tiles_y;
-    const int n_pad = (n_tiles + 7) & ~7;
+    const int n_wg = column_grid(tiles_x, tiles_y);
     ListArgs la{nullptr, nullptr, 0};
     const ListLayout L = list_layout(H, W);
     ListViews v;
@@ -570,18 +573,18 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
     const bool small = fp.radius <= 16;
     if (prec == JBFD_FP32) {
         if (small)
-            k_jbf_fwd<16, JBFD_FP32><<<n_pad, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, la, out, mask, a2);
+            k_jbf_fwd<16, JBFD_FP32><<<n_wg, 256, 0, s>>>(
+                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, a2);
         else
-            k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP32><<<n_pad, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, la, out, mask, a2);
+            k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP32><<<n_wg, 256, 0, s>>>(
+                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, a2);
     } else {
         if (small)
-            k_jbf_fwd<16, JBFD_FP16_RANGE><<<n_pad, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, la, out, mask, nullptr);
+            k_jbf_fwd<16, JBFD_FP16_RANGE><<<n_wg, 256, 0, s>>>(
+                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, nullptr);
         else
-            k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<n_pad, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, la, out, mask, nullptr);
+            k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<n_wg, 256, 0, s>>>(
+                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, nullptr);
     }
     return hipGetLastError();
 }

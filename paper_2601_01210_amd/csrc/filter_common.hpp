@@ -70,6 +70,26 @@ __device__ inline int xcd_tile(int wg, int n_pad) {
     return (wg & 7) * (n_pad >> 3) + (wg >> 3);
 }
 
+// Column-interleaved tile order, for kernels whose work follows the sample
+// density: XCD c (which runs workgroups c, c + 8, ...) takes the tile
+// columns tx = c (mod 8), row by row. Every XCD gets an even share of the
+// columns whatever rows hold the samples (a band split leaves the XCDs of
+// an empty sky idle), and vertically adjacent tiles, which read overlapping
+// list ranges, stay in one L2. column_grid workgroups cover every tile;
+// column_tile returns false for the few left over.
+inline int column_grid(int tiles_x, int tiles_y) {
+    return 8 * ((tiles_x + 7) / 8) * tiles_y;
+}
+
+__device__ inline bool column_tile(int wg, int tiles_x, int tiles_y, int &tx, int &ty) {
+    const int c = wg & 7, k = wg >> 3;
+    const int ncol = (tiles_x - c + 7) >> 3;   // columns c, c + 8, ... below tiles_x
+    if (ncol <= 0 || k >= ncol * tiles_y) return false;
+    ty = k / ncol;
+    tx = c + 8 * (k - ty * ncol);
+    return true;
+}
+
 // bits [a, b) of a 64-bit word (a, b clamped to [0, 64])
 __device__ inline uint64_t bit_range(int a, int b) {
     a = max(a, 0);
@@ -146,6 +166,34 @@ struct ListArgs {
     const uint32_t *recs;   // nullptr: stream the halo instead
     const int *rowoff;      // [n_strips][H + 1]
     int64_t capacity;       // records the workspace holds
+};
+
+// Pass-1 exponent of one sample (FP32 forms; the forward and the backward
+// both use it, so they form bit-identical weights): max(a, -60) + g for the
+// colour exponent a = fma(2kr, t, M) and the table entry g. It is evaluated
+// as
+//     y = clamp01((m - a) / 60),   e = g - 60 y   (= a - m + g above the floor)
+// with the clamp done by the fma's output modifier, two instructions where
+// max-then-add takes three. The heavy weights have y near 0, where y and
+// g - 60 y round as finely as a and a + g do. The margin m > 0 (a lane
+// constant) keeps y above 0 although rounding of the lane constant M can
+// leave a slightly above 0; it scales every weight of the lane by 2^-m,
+// which cancels in num/den.
+struct Pass1Exp {
+    float k, c;   // y = clamp01(fma(k, t, c))
+    __device__ Pass1Exp(float kr2, float M)
+        : k(kr2 * (1.0f / kClampExp)), c(lane_c(M)) {}
+    // c for the lane constant M: (m - M) / 60 with m = 2^-10 + |M| 2^-18
+    // (above the rounding residue of M, which is at most |M| 2^-24)
+    __device__ static float lane_c(float M) {
+        const float m = __builtin_fmaf(__builtin_fabsf(M), 0x1p-18f, 0x1p-10f);
+        return (m - M) * (-1.0f / kClampExp);
+    }
+    __device__ static float eval(float k, float c, float t, float g) {
+        const float y = __builtin_amdgcn_fmed3f(__builtin_fmaf(k, t, c), 0.0f, 1.0f);
+        return __builtin_fmaf(kClampExp, y, g);
+    }
+    __device__ float operator()(float t, float g) const { return eval(k, c, t, g); }
 };
 
 // Consume four samples: exponents a = fma(2kr, t, M) + g, rescale when one

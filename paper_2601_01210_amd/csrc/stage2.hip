@@ -175,14 +175,14 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
         gs[s] = fmaxf(-fp.ks * (float)s, kClampExp);
 
     float num = 0.0f, den = 0.0f;
+    const Pass1Exp p1(kr2, Mfast);
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
             const uint4 q = tile[(ly + R + dy) * E + lx + R + dx];
             const float tq = dot2h(prg, q.x, dot2h(pb0, q.y, __uint_as_float(q.w)));
-            const float a = fmaxf(__builtin_fmaf(kr2, tq, Mfast), kClampExp) +
-                            gs[dx * dx + dy * dy];
+            const float a = p1(tq, gs[dx * dx + dy * dy]);
             const float w = __builtin_amdgcn_exp2f(a);
             const _Float16 vf = __builtin_bit_cast(h2, q.y)[1];
             num = __builtin_fmaf(w, __uint_as_float(q.z), num);
