@@ -494,14 +494,24 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     float M = Mfast;
     if (__builtin_amdgcn_ballot_w64(weak) != 0) {
         float M2 = kShiftInit - fp.kr * p2, num2 = 0.0f, den2 = 0.0f;
-        bw.walk<true>(
-            [&](const float (&t)[4], const float (&g)[4], const float (&d)[4],
-                const uint32_t (&)[4]) {
-                if (weak) consume4(t, g, d, kr2, M2, num2, den2);
-            },
-            [&](float t, float g, float d, uint32_t) {
-                if (weak) consume1(t, g, d, kr2, M2, num2, den2);
-            });
+        auto eat4 = [&](const float (&t)[4], const float (&g)[4], const float (&d)[4],
+                        const uint32_t (&)[4]) {
+            if (weak) consume4(t, g, d, kr2, M2, num2, den2);
+        };
+        auto eat1 = [&](float t, float g, float d, uint32_t) {
+            if (weak) consume1(t, g, d, kr2, M2, num2, den2);
+        };
+        // When no entry inside the window is clamped (the corners hold the
+        // largest distance, 2r^2), the FP32 table holds exactly the
+        // exponents exact_g forms, with the same float operations, so the
+        // exact pass reads them from the table.
+        bool table_exact = false;
+        if constexpr (PREC == JBFD_FP32)
+            table_exact = -fp.ks * (float)(2 * r * r) >= kClampExp;
+        if (table_exact)
+            bw.walk<false>(eat4, eat1);
+        else
+            bw.walk<true>(eat4, eat1);
         if (weak) {
             num = num2;
             den = den2;
