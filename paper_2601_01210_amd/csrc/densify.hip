@@ -64,27 +64,36 @@ size_t densify_ws_bytes(int32_t H, int32_t W, int32_t r, int64_t max_samples) {
     return L.recs + (size_t)max_samples * strips_per_column(r) * kRecWords * 4;
 }
 
-// Load the validity bytes of rows [y_first, y_first + n) over the group's
-// 128 halo columns [c0, c0 + 128) and ballot them into 128-bit row masks
-// (columns outside the image read as invalid). All loads are issued before
-// the first ballot.
+// Load the validity bytes of rows [y_first, y_first + NROWS) over the
+// group's 128 halo columns [c0, c0 + 128), one byte per lane and row for
+// columns c0 + lane and c0 + 64 + lane. Every load is unconditional from a
+// clamped (in-image) address, so all of them are in flight together;
+// row_ballots masks the columns and rows outside the image.
 template <int NROWS>
-__device__ __forceinline__ void group_row_masks(const uint8_t *__restrict__ B, int H, int W,
-                                       int c0, int y_first, uint64_t (&lo)[NROWS],
-                                       uint64_t (&hi)[NROWS]) {
+__device__ __forceinline__ void group_row_bytes(const uint8_t *__restrict__ B, int H,
+                                                int W, int c0, int y_first,
+                                                uint8_t (&va)[NROWS],
+                                                uint8_t (&vb)[NROWS]) {
     const int lane = threadIdx.x & 63;
-    const int xa = c0 + lane, xb = c0 + 64 + lane;
-    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
-    // every load is unconditional from a clamped (in-image) address, so all
-    // of them are in flight together; out-of-image lanes are masked after
-    const int xa_c = min(max(xa, 0), W - 1), xb_c = min(max(xb, 0), W - 1);
-    uint8_t va[NROWS], vb[NROWS];
+    const int xa_c = min(max(c0 + lane, 0), W - 1);
+    const int xb_c = min(max(c0 + 64 + lane, 0), W - 1);
 #pragma unroll
     for (int k = 0; k < NROWS; ++k) {
         const uint8_t *row = B + (int64_t)min(y_first + k, H - 1) * W;
         va[k] = row[xa_c];
         vb[k] = row[xb_c];
     }
+}
+
+// ... and ballot them into 128-bit row masks
+template <int NROWS>
+__device__ __forceinline__ void row_ballots(int H, int W, int c0, int y_first,
+                                            const uint8_t (&va)[NROWS],
+                                            const uint8_t (&vb)[NROWS],
+                                            uint64_t (&lo)[NROWS], uint64_t (&hi)[NROWS]) {
+    const int lane = threadIdx.x & 63;
+    const int xa = c0 + lane, xb = c0 + 64 + lane;
+    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
 #pragma unroll
     for (int k = 0; k < NROWS; ++k) {
         const bool iny = y_first + k < H;
@@ -107,9 +116,11 @@ __device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, i
     const int lane = threadIdx.x & 63;
     const int c0 = 64 * g - r;
     constexpr int kRowsPerWave = kBandRows / 4;
+    const int y_first = band * kBandRows + wid * kRowsPerWave;
+    uint8_t va[kRowsPerWave], vb[kRowsPerWave];
+    group_row_bytes<kRowsPerWave>(B, H, W, c0, y_first, va, vb);
     uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
-    group_row_masks<kRowsPerWave>(B, H, W, c0, band * kBandRows + wid * kRowsPerWave,
-                                  lo, hi);
+    row_ballots<kRowsPerWave>(H, W, c0, y_first, va, vb, lo, hi);
     int acc = 0;
     if (lane < kGroupStrips) {
 #pragma unroll
@@ -165,44 +176,69 @@ __device__ __forceinline__ void list_scatter_unit(
     const int y_band = band * kBandRows;
     const int s_first = kGroupStrips * g;
 
-    // (1) records of all strips before the group: the group-and-band
-    // totals of groups < g (the first g*n_bands entries of grpcnt)
-    // (eight loads per thread in flight at once: one round trip for a
-    // Full-HD image's 30 x 68 entries)
-    int acc = 0;
+    // The prologue's loads are all issued before the first wait: (3) the
+    // validity bytes of the band's rows (wave w: rows 4w .. 4w+3), (1) the
+    // group-and-band totals of the groups before g, whose sum is the number
+    // of records of all strips before the group, and (2) per strip of the
+    // group (32 threads each), its band counts, for its total and the part
+    // in bands before ours. One batch of (1) and (2) covers images of up to
+    // 2048 group-band entries before the group and 128 bands (Full-HD:
+    // 1972 and 68); larger images loop over further batches afterwards.
+    constexpr int kRowsPerWave = kBandRows / 4;
+    const int y_rows = y_band + wid * kRowsPerWave;
+    uint8_t va[kRowsPerWave], vb[kRowsPerWave];
+    group_row_bytes<kRowsPerWave>(B, H, W, c0, y_rows, va, vb);
     const int n_before = g * n_bands;
-    for (int k0 = 0; k0 < n_before; k0 += 8 * 256) {
-        int a[8];
+    int a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int k = 256 * u + t;
+        a[u] = grpcnt[k < n_before ? k : 0];
+    }
+    const int j = t >> 5, k32 = t & 31;
+    const int sj = s_first + j;
+    const bool sj_ok = sj < n_strips;
+    const int *bc = bandcnt + (int64_t)(sj_ok ? sj : 0) * n_bands;
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int b = 32 * u + k32;
+        c[u] = bc[b < n_bands ? b : 0];
+    }
+    int acc = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += 256 * u + t < n_before ? a[u] : 0;
+    for (int k0 = 8 * 256; k0 < n_before; k0 += 8 * 256) {
+        int e[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int k = k0 + 256 * u + t;
-            a[u] = grpcnt[k < n_before ? k : 0];
-            a[u] = k < n_before ? a[u] : 0;
+            e[u] = grpcnt[k < n_before ? k : 0];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += a[u];
+        for (int u = 0; u < 8; ++u) acc += k0 + 256 * u + t < n_before ? e[u] : 0;
     }
-    // (2) per strip of the group: total and the part in bands before ours
-    //     (32 threads per strip)
-    const int j = t >> 5, k32 = t & 31;
-    const int sj = s_first + j;
     int tot = 0, pre = 0;
-    if (sj < n_strips) {
-        const int *bc = bandcnt + (int64_t)sj * n_bands;
-        for (int b0 = 0; b0 < n_bands; b0 += 4 * 32) {
-            int c[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int b = b0 + 32 * u + k32;
-                c[u] = bc[b < n_bands ? b : 0];
-                c[u] = b < n_bands ? c[u] : 0;
-            }
+    for (int u = 0; u < 4; ++u) {
+        const int b = 32 * u + k32;
+        const int v = sj_ok && b < n_bands ? c[u] : 0;
+        tot += v;
+        pre += b < band ? v : 0;
+    }
+    for (int b0 = 4 * 32; b0 < n_bands; b0 += 4 * 32) {
+        int e[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int b = b0 + 32 * u + k32;
-                tot += c[u];
-                pre += b < band ? c[u] : 0;
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + 32 * u + k32;
+            e[u] = bc[b < n_bands ? b : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + 32 * u + k32;
+            const int v = sj_ok && b < n_bands ? e[u] : 0;
+            tot += v;
+            pre += b < band ? v : 0;
         }
     }
 #pragma unroll
@@ -217,20 +253,18 @@ __device__ __forceinline__ void list_scatter_unit(
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) red[wid] = acc;
-    // (3) validity masks of the band's rows (wave w: rows 16w .. 16w+15)
     {
-        constexpr int kRowsPerWave = kBandRows / 4;
         uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
-        group_row_masks<kRowsPerWave>(B, H, W, c0, y_band + wid * kRowsPerWave, lo, hi);
+        row_ballots<kRowsPerWave>(H, W, c0, y_rows, va, vb, lo, hi);
         if (lane < kRowsPerWave) {
-            uint64_t a = 0, b = 0;
+            uint64_t ma = 0, mb = 0;
 #pragma unroll
             for (int k = 0; k < kRowsPerWave; ++k) {
-                a = lane == k ? lo[k] : a;
-                b = lane == k ? hi[k] : b;
+                ma = lane == k ? lo[k] : ma;
+                mb = lane == k ? hi[k] : mb;
             }
-            mlo[wid * kRowsPerWave + lane] = a;
-            mhi[wid * kRowsPerWave + lane] = b;
+            mlo[wid * kRowsPerWave + lane] = ma;
+            mhi[wid * kRowsPerWave + lane] = mb;
         }
     }
     __syncthreads();
