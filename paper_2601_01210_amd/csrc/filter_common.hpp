@@ -587,21 +587,26 @@ __device__ inline void build_table(float *G, int r, int ts, float ks, bool weigh
     const int tdim = 2 * r + 15;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // a lane owns a column (dx), a wave walks rows (dy uniform), so the
-    // per-entry work is one add, the exponent, its clamp and a select
+    // a lane owns a column (dx), a wave walks rows (dy uniform): a row
+    // outside the window is stored without arithmetic, and inside it an
+    // entry costs one add, the exponent, its clamp and a select.
+    // (float)dx^2 + (float)dy^2 is exact (both below 2^24), so the entries
+    // equal -ks (float)(dx^2 + dy^2), the exact pass's spatial exponents.
+    const float g_out = weights ? 0.0f : -__builtin_inff();
     for (int ux = lane; ux < tdim; ux += 64) {
         const int dx = ux - r - 7;
         const bool in_x = dx >= -r && dx <= r;
-        const int dx2 = dx * dx;
+        const float fx = (float)(dx * dx);
         for (int uy = wid; uy < tdim; uy += 4) {
             const int dy = uy - r - 7;
-            const bool in = in_x && dy >= -r && dy <= r;
-            const float e = -ks * (float)(dx2 + dy * dy);
-            float g;
-            if (!weights)
-                g = in ? fmaxf(e, kClampExp) : -__builtin_inff();
-            else
-                g = in ? __builtin_amdgcn_exp2f(fmaxf(e, -100.0f)) : 0.0f;
+            float g = g_out;
+            if (dy >= -r && dy <= r) {   // wave-uniform
+                const float e = -ks * (fx + (float)(dy * dy));
+                if (!weights)
+                    g = in_x ? fmaxf(e, kClampExp) : g_out;
+                else
+                    g = in_x ? __builtin_amdgcn_exp2f(fmaxf(e, -100.0f)) : g_out;
+            }
             G[uy * ts + ux] = g;
         }
     }
