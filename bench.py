@@ -140,7 +140,7 @@ def committed_counters(kernel: str) -> dict:
 
 
 def _fit_view(seed):
-    """A config-1-generator scene at Full-HD (6 boxes, one 16-beam sweep)."""
+    """The small-scene generator at Full-HD (6 boxes, one 16-beam sweep)."""
     return S.small_view(np.random.default_rng(seed), 1920, 1080)
 
 
