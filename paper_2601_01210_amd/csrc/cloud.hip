@@ -160,9 +160,7 @@ __global__ __launch_bounds__(256) void k_cloud_count(const float *__restrict__ D
     const uint32_t p0 = (uint32_t)blockIdx.x * kCloudChunk + 4u * threadIdx.x;
     const uint32_t bits = contour_bits(D, M, H, W, npix, p0, tau);
     keep[(size_t)blockIdx.x * 256 + threadIdx.x] = (uint8_t)bits;
-    int cnt = __builtin_popcount(bits);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    const int cnt = wave_sum(__builtin_popcount(bits));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];

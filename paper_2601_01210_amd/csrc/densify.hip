@@ -137,9 +137,8 @@ __device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, i
             sum = part[0][q] + part[1][q] + part[2][q] + part[3][q];
             bandcnt[(int64_t)s * n_bands + band] = sum;
         }
-#pragma unroll
-        for (int off = 4; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 8);
-        if (q == 0) grpcnt[(int64_t)g * n_bands + band] = sum;
+        const int gsum = wave_sum(sum);   // lanes 8 .. 63 hold 0
+        if (q == 0) grpcnt[(int64_t)g * n_bands + band] = gsum;
     }
 }
 
@@ -241,17 +240,21 @@ __device__ __forceinline__ void list_scatter_unit(
             pre += b < band ? v : 0;
         }
     }
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) {
-        tot += __shfl_xor(tot, off, 32);
-        pre += __shfl_xor(pre, off, 32);
+    // strips j = 2w (lanes 0-31) and 2w + 1 (lanes 32-63) of wave w: the
+    // scans' lanes 31 and 63 hold the first half's and the whole wave's sums
+    {
+        const int st = wave_inclusive_scan(tot), sp = wave_inclusive_scan(pre);
+        const int t_lo = __builtin_amdgcn_readlane(st, 31);
+        const int p_lo = __builtin_amdgcn_readlane(sp, 31);
+        if (lane == 0) {
+            stot[j] = t_lo;
+            spre[j] = p_lo;
+        } else if (lane == 32) {
+            stot[j] = __builtin_amdgcn_readlane(st, 63) - t_lo;
+            spre[j] = __builtin_amdgcn_readlane(sp, 63) - p_lo;
+        }
     }
-    if (k32 == 0) {
-        stot[j] = tot;
-        spre[j] = pre;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    acc = wave_sum(acc);
     if (lane == 0) red[wid] = acc;
     {
         uint64_t lo[kRowsPerWave], hi[kRowsPerWave];

@@ -105,15 +105,24 @@ __device__ inline int popc128(uint64_t lo, uint64_t hi, int a, int b) {
            __builtin_popcountll(hi & bit_range(a - 64, b - 64));
 }
 
-// inclusive scan across the 64 lanes of a wave
+// Inclusive scan across the 64 lanes of a wave (every lane active), with
+// DPP moves instead of LDS permutes: shifts by 1, 2, 4 and 8 lanes within
+// each row of 16 (Hillis-Steele), then lane 15's sum added to rows 1 and 3
+// and lane 31's to rows 2 and 3 (row broadcasts). A lane whose source is
+// outside its row takes the old value 0.
 __device__ inline int wave_inclusive_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
     return v;
+}
+
+// sum over the 64 lanes of a wave (every lane active), wave-uniform
+__device__ inline int wave_sum(int v) {
+    return __builtin_amdgcn_readlane(wave_inclusive_scan(v), 63);
 }
 
 // ---------------------------------------------------------------------------
