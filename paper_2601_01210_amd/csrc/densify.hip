@@ -541,14 +541,11 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
         // When no entry inside the window is clamped (the corners hold the
         // largest distance, 2r^2), the FP32 table holds exactly the
         // exponents exact_g forms, with the same float operations, so the
-        // exact pass reads them from the table.
+        // exact pass's list walk reads them from the table.
         bool table_exact = false;
         if constexpr (PREC == JBFD_FP32)
             table_exact = -fp.ks * (float)(2 * r * r) >= kClampExp;
-        if (table_exact)
-            bw.walk<false>(eat4, eat1);
-        else
-            bw.walk<true>(eat4, eat1);
+        bw.walk_exact(table_exact, eat4, eat1);
         if (weak) {
             num = num2;
             den = den2;

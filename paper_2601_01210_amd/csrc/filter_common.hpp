@@ -486,6 +486,22 @@ struct BlockWalker {
         stream<EXACT>(eat4, eat1);
     }
 
+    // the exact pass: exact spatial exponents, read from the table when it
+    // holds them exactly (table_exact) on the list walk; the stream always
+    // recomputes them (one streaming loop fewer in the kernel)
+    template <class E4, class E1>
+    __device__ void walk_exact(bool table_exact, E4 &&eat4, E1 &&eat1) const {
+        int lo, hi;
+        if (list_range(lo, hi)) {
+            if (table_exact)
+                walk_list<false>(lo, hi, eat4, eat1);
+            else
+                walk_list<true>(lo, hi, eat4, eat1);
+            return;
+        }
+        stream<true>(eat4, eat1);
+    }
+
     // first pass: the split list walk, or the stream
     template <class SA, class SB, class E4, class E1>
     __device__ void walk_split(SA &&stage_a, SB &&stage_b, E4 &&eat4, E1 &&eat1,
