@@ -8,6 +8,8 @@
  *   1. jbfd_project  - the merged LiDAR points of a viewpoint become one
  *                      sparse depth image in its camera (Sec. 2), the
  *                      nearest point winning each pixel (z-buffer);
+ *                      jbfd_project_recycled and jbfd_zbuf_clear do the same
+ *                      for a frame loop that reuses its key buffer;
  *   2. jbfd_densify  - RGB-guided joint bilateral filter over that sparse
  *                      depth image (Eq. 1-4, organised as Algorithm 1),
  *                      giving a dense depth image and a validity mask;
@@ -64,7 +66,7 @@
 extern "C" {
 #endif
 
-#define JBFD_ABI_VERSION 2
+#define JBFD_ABI_VERSION 3
 
 /* Largest filter radius: the halo of one 8x8 output block must fit the
  * per-workgroup spatial table in LDS. */
@@ -158,6 +160,28 @@ jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
                          const jbfd_intrinsics *K, uint64_t *zbuf,
                          float *sparse_depth, uint8_t *sparse_valid,
                          void *stream);
+
+/*
+ * jbfd_project for a frame loop that reuses its key buffer (same
+ * projection, same sparse_depth and sparse_valid, bit for bit). zbuf must
+ * hold the empty key UINT64_MAX in every pixel on entry: the state
+ * jbfd_zbuf_clear and every call of this function leave it in (a buffer
+ * fresh from jbfd_project holds the winning keys instead). The clearing
+ * pass is skipped, and the decode writes the empty key back over each key
+ * it reads, so the buffer is touched once less per frame and the winning
+ * keys are not returned. sparse_depth and sparse_valid are required (NULL
+ * is JBFD_EINVAL); the other arguments are those of jbfd_project. Calls
+ * that share a zbuf must be ordered (one stream, or synchronised).
+ */
+jbfd_status jbfd_project_recycled(const float *pts_xyz, int64_t n,
+                                  const double cam_from_world[12],
+                                  const jbfd_intrinsics *K, uint64_t *zbuf,
+                                  float *sparse_depth, uint8_t *sparse_valid,
+                                  void *stream);
+
+/* Set every key of an H x W key buffer (device) to the empty key
+ * UINT64_MAX, for jbfd_project_recycled. */
+jbfd_status jbfd_zbuf_clear(uint64_t *zbuf, int32_t H, int32_t W, void *stream);
 
 /*
  * Joint bilateral filter over a sparse depth image (Eq. 1-4; the window and

@@ -82,6 +82,10 @@ def lib():
         L.jbfd_project.restype = C.c_int
         L.jbfd_project.argtypes = [vp, i64, C.POINTER(C.c_double),
                                    C.POINTER(Intrinsics), vp, vp, vp, vp]
+        L.jbfd_project_recycled.restype = C.c_int
+        L.jbfd_project_recycled.argtypes = L.jbfd_project.argtypes
+        L.jbfd_zbuf_clear.restype = C.c_int
+        L.jbfd_zbuf_clear.argtypes = [vp, i32, i32, vp]
         L.jbfd_densify.restype = C.c_int
         L.jbfd_densify.argtypes = [vp, vp, vp, i32, i32, i32, f32, f32,
                                    C.c_int, vp, vp, vp, vp, sz, C.c_uint32,
@@ -179,12 +183,15 @@ def _pose_array(pose) -> C.Array:
 
 def project(points, pose, intrinsics: Sequence[float], width: int,
             height: int, zbuf=None, depth=None, valid=None,
-            want_sparse: bool = True):
+            want_sparse: bool = True, recycle: bool = False):
     """Nearest-depth projection (jbfd_project).
 
     points      (N,3) float32 device tensor, world xyz in merged order
     pose        3x4 camera-from-world [R|t] (host array-like)
     intrinsics  (fx, fy, cx, cy)
+    recycle     use jbfd_project_recycled: ``zbuf`` (required) holds only
+                empty keys (see :func:`zbuf_clear`) and is left so; the
+                winning keys are not returned
     Returns (zbuf uint64-as-int64 (H,W), depth float32 (H,W), valid uint8
     (H,W)); depth/valid are None when ``want_sparse`` is False.
     """
@@ -194,6 +201,8 @@ def project(points, pose, intrinsics: Sequence[float], width: int,
         raise ValueError("points must have shape (N, 3)")
     dev = points.device
     if zbuf is None:
+        if recycle:
+            raise ValueError("recycle needs a key buffer cleared by zbuf_clear")
         zbuf = torch.empty((height, width), dtype=torch.int64, device=dev)
     _need(zbuf, torch.int64, (height, width), "zbuf")
     if want_sparse:
@@ -206,10 +215,26 @@ def project(points, pose, intrinsics: Sequence[float], width: int,
     K = Intrinsics(float(intrinsics[0]), float(intrinsics[1]),
                    float(intrinsics[2]), float(intrinsics[3]), int(width),
                    int(height))
-    _check(lib().jbfd_project(_ptr(points), int(points.shape[0]),
-                              _pose_array(pose), C.byref(K), _ptr(zbuf),
-                              _ptr(depth), _ptr(valid), _stream(dev)))
+    if recycle:
+        if not want_sparse:
+            raise ValueError("recycle needs the sparse depth and mask")
+        fn = lib().jbfd_project_recycled
+    else:
+        fn = lib().jbfd_project
+    _check(fn(_ptr(points), int(points.shape[0]), _pose_array(pose), C.byref(K),
+              _ptr(zbuf), _ptr(depth), _ptr(valid), _stream(dev)))
     return zbuf, depth, valid
+
+
+def zbuf_clear(zbuf):
+    """Fill a (H,W) int64 device key buffer with empty keys (jbfd_zbuf_clear)."""
+    torch = _torch()
+    _need(zbuf, torch.int64, None, "zbuf")
+    if zbuf.dim() != 2:
+        raise ValueError("zbuf must have shape (H, W)")
+    h, w = zbuf.shape
+    _check(lib().jbfd_zbuf_clear(_ptr(zbuf), h, w, _stream(zbuf.device)))
+    return zbuf
 
 
 def densify_ws_bytes(h: int, w: int, radius: int, max_samples: int) -> int:

@@ -89,32 +89,66 @@ const char *jbfd_status_string(jbfd_status s) {
 
 const char *jbfd_last_error(void) { return g_err; }
 
+// argument checks shared by the projection entry points
+static jbfd_status check_project(const char *name, const float *pts_xyz, int64_t n,
+                                 const double cam_from_world[12],
+                                 const jbfd_intrinsics *K, const uint64_t *zbuf) {
+    if (!cam_from_world || !K || !zbuf)
+        return fail(JBFD_EINVAL, "%s: null pose, intrinsics or zbuf", name);
+    if (n < 0 || n >= ((int64_t)1 << 32))
+        return fail(JBFD_EINVAL, "%s: n = %lld outside 0..2^32-1", name, (long long)n);
+    if (n > 0 && !pts_xyz) return fail(JBFD_EINVAL, "%s: null points", name);
+    jbfd_status st = check_image(K->height, K->width);
+    if (st != JBFD_OK) return st;
+    for (int t = 0; t < 12; ++t)
+        if (!isfinite(cam_from_world[t]))
+            return fail(JBFD_EINVAL, "%s: pose entry %d not finite", name, t);
+    if (!isfinite(K->fx) || !isfinite(K->fy) || !isfinite(K->cx) || !isfinite(K->cy))
+        return fail(JBFD_EINVAL, "%s: intrinsics not finite", name);
+    return JBFD_OK;
+}
+
+static jbfd_status project_common(const char *name, const float *pts_xyz, int64_t n,
+                                  const double cam_from_world[12],
+                                  const jbfd_intrinsics *K, uint64_t *zbuf,
+                                  float *sparse_depth, uint8_t *sparse_valid,
+                                  bool recycle, void *stream) {
+    const jbfd_status st = check_project(name, pts_xyz, n, cam_from_world, K, zbuf);
+    if (st != JBFD_OK) return st;
+    jbfd::Pose P;
+    for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
+    jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
+    return hip_status(jbfd::launch_project(pts_xyz, n, P, I, zbuf, sparse_depth,
+                                           sparse_valid, recycle, (hipStream_t)stream),
+                      name);
+}
+
 jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
                          const double cam_from_world[12],
                          const jbfd_intrinsics *K, uint64_t *zbuf,
                          float *sparse_depth, uint8_t *sparse_valid,
                          void *stream) {
-    if (!cam_from_world || !K || !zbuf)
-        return fail(JBFD_EINVAL, "jbfd_project: null pose, intrinsics or zbuf");
-    if (n < 0 || n >= ((int64_t)1 << 32))
-        return fail(JBFD_EINVAL, "jbfd_project: n = %lld outside 0..2^32-1",
-                    (long long)n);
-    if (n > 0 && !pts_xyz)
-        return fail(JBFD_EINVAL, "jbfd_project: null points");
-    jbfd_status st = check_image(K->height, K->width);
+    return project_common("jbfd_project", pts_xyz, n, cam_from_world, K, zbuf,
+                          sparse_depth, sparse_valid, false, stream);
+}
+
+jbfd_status jbfd_project_recycled(const float *pts_xyz, int64_t n,
+                                  const double cam_from_world[12],
+                                  const jbfd_intrinsics *K, uint64_t *zbuf,
+                                  float *sparse_depth, uint8_t *sparse_valid,
+                                  void *stream) {
+    if (!sparse_depth || !sparse_valid)
+        return fail(JBFD_EINVAL, "jbfd_project_recycled: null sparse_depth or sparse_valid");
+    return project_common("jbfd_project_recycled", pts_xyz, n, cam_from_world, K,
+                          zbuf, sparse_depth, sparse_valid, true, stream);
+}
+
+jbfd_status jbfd_zbuf_clear(uint64_t *zbuf, int32_t H, int32_t W, void *stream) {
+    if (!zbuf) return fail(JBFD_EINVAL, "jbfd_zbuf_clear: null zbuf");
+    const jbfd_status st = check_image(H, W);
     if (st != JBFD_OK) return st;
-    for (int t = 0; t < 12; ++t)
-        if (!isfinite(cam_from_world[t]))
-            return fail(JBFD_EINVAL, "jbfd_project: pose entry %d not finite", t);
-    if (!isfinite(K->fx) || !isfinite(K->fy) || !isfinite(K->cx) ||
-        !isfinite(K->cy))
-        return fail(JBFD_EINVAL, "jbfd_project: intrinsics not finite");
-    jbfd::Pose P;
-    for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
-    jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
-    return hip_status(jbfd::launch_project(pts_xyz, n, P, I, zbuf, sparse_depth,
-                                           sparse_valid, (hipStream_t)stream),
-                      "jbfd_project");
+    return hip_status(jbfd::launch_fill_keys(zbuf, (int64_t)H * W, (hipStream_t)stream),
+                      "jbfd_zbuf_clear");
 }
 
 jbfd_status jbfd_densify(const float *sparse_depth, const uint8_t *sparse_valid,

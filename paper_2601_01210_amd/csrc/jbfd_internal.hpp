@@ -32,7 +32,8 @@ struct FilterParams {
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
                           const Intr &K, uint64_t *zbuf, float *depth,
-                          uint8_t *valid, hipStream_t s);
+                          uint8_t *valid, bool recycle, hipStream_t s);
+hipError_t launch_fill_keys(uint64_t *zbuf, int64_t npix, hipStream_t s);
 
 hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                           int32_t H, int32_t W, const FilterParams &fp,

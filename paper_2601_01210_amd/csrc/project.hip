@@ -12,16 +12,24 @@
 //                pixel's key; positive floats order like their bit
 //                patterns, so the minimum key is the nearest point and an
 //                exact tie goes to the smaller index;
-//   k_decode     key image -> float depth (0 where empty) and 0/1 mask.
+//   k_decode     key image -> float depth (0 where empty) and 0/1 mask; the
+//                recycling form also writes the empty key back, so a frame
+//                loop that reuses its key buffer needs no k_fill_keys.
 //
 // k_project_motion is k_project for afterimage removal (Sec. 4.1): points of
 // older sweeps that land in a moving pixel are dropped before the atomic.
 //
 // Traffic per frame: 12N bytes of points, 8HW to clear, the atomics, 8HW
 // read + 5HW written by the decode.
+#include <type_traits>
+
 #include "jbfd_internal.hpp"
 
 namespace jbfd {
+
+// key buffer as the decode sees it: read-only, or written back with RESET
+template <bool RESET>
+using KeyPtr = std::conditional_t<RESET, uint64_t *, const uint64_t *__restrict__>;
 
 // Eight keys per thread per step, as four 16-byte stores that are each
 // contiguous across the workgroup (2048 keys per workgroup and step).
@@ -113,10 +121,12 @@ __global__ __launch_bounds__(256) void k_project_motion(
 }
 
 // Decode pixels [p0, min(p0+4, npix)): two 16-byte key loads, one 16-byte
-// depth store and one 4-byte mask store when aligned, else per pixel.
-__device__ inline void decode4(const uint64_t *__restrict__ keys, int64_t npix,
-                               int64_t p0, bool vec, float *__restrict__ depth,
-                               uint8_t *__restrict__ valid) {
+// depth store and one 4-byte mask store when aligned, else per pixel. With
+// RESET the empty key is written back over each key read, so the buffer
+// needs no clearing before the next projection into it.
+template <bool RESET>
+__device__ inline void decode4(KeyPtr<RESET> keys, int64_t npix, int64_t p0, bool vec,
+                               float *__restrict__ depth, uint8_t *__restrict__ valid) {
     if (vec && p0 + 4 <= npix) {
         const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(keys + p0);
         const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(keys + p0 + 2);
@@ -131,12 +141,18 @@ __device__ inline void decode4(const uint64_t *__restrict__ keys, int64_t npix,
         if (depth)
             *reinterpret_cast<float4 *>(depth + p0) = make_float4(d[0], d[1], d[2], d[3]);
         if (valid) *reinterpret_cast<uint32_t *>(valid + p0) = m;
+        if constexpr (RESET) {
+            const ulonglong2 e = make_ulonglong2(kEmptyKey, kEmptyKey);
+            *reinterpret_cast<ulonglong2 *>(keys + p0) = e;
+            *reinterpret_cast<ulonglong2 *>(keys + p0 + 2) = e;
+        }
     } else {
         for (int64_t p = p0; p < npix && p < p0 + 4; ++p) {
             const uint64_t k = keys[p];
             const bool hit = k != kEmptyKey;
             if (depth) depth[p] = hit ? __uint_as_float((uint32_t)(k >> 32)) : 0.0f;
             if (valid) valid[p] = (uint8_t)hit;
+            if constexpr (RESET) keys[p] = kEmptyKey;
         }
     }
 }
@@ -148,8 +164,8 @@ __device__ inline bool decode_vec_ok(const uint64_t *keys, const float *depth,
            ((reinterpret_cast<uintptr_t>(keys) & 15) == 0);
 }
 
-__global__ __launch_bounds__(256) void k_decode(const uint64_t *__restrict__ keys,
-                                                int64_t npix,
+template <bool RESET>
+__global__ __launch_bounds__(256) void k_decode(KeyPtr<RESET> keys, int64_t npix,
                                                 float *__restrict__ depth,
                                                 uint8_t *__restrict__ valid) {
     const int64_t groups = (npix + 3) / 4;
@@ -157,7 +173,7 @@ __global__ __launch_bounds__(256) void k_decode(const uint64_t *__restrict__ key
     const bool vec = decode_vec_ok(keys, depth, valid);
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
          g += stride)
-        decode4(keys, npix, g * 4, vec, depth, valid);
+        decode4<RESET>(keys, npix, g * 4, vec, depth, valid);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,7 +238,7 @@ __global__ __launch_bounds__(256) void k_batch_decode(const BatchHeader *__restr
         const int64_t p0 = (int64_t)(c - bv.px_chunk_off) * kBatchChunk +
                            4 * (int64_t)threadIdx.x;
         if (p0 < npix)
-            decode4(bv.zbuf, npix, p0, decode_vec_ok(bv.zbuf, bv.sd, bv.sv),
+            decode4<false>(bv.zbuf, npix, p0, decode_vec_ok(bv.zbuf, bv.sd, bv.sv),
                     bv.sd, bv.sv);
     }
 }
@@ -236,14 +252,21 @@ static int grid_for(int64_t work, int per_block) {
 
 hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
                           const Intr &K, uint64_t *zbuf, float *depth,
-                          uint8_t *valid, hipStream_t s) {
+                          uint8_t *valid, bool recycle, hipStream_t s) {
     const int64_t npix = (int64_t)K.w * K.h;
-    k_fill_keys<<<grid_for(npix, 2048), 256, 0, s>>>(zbuf, npix);
+    if (!recycle) k_fill_keys<<<grid_for(npix, 2048), 256, 0, s>>>(zbuf, npix);
     if (n > 0)
         k_project<<<grid_for(n, 256), 256, 0, s>>>(
             pts, n, pose, K, reinterpret_cast<unsigned long long *>(zbuf));
-    if (depth || valid)
-        k_decode<<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
+    if (recycle)
+        k_decode<true><<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
+    else if (depth || valid)
+        k_decode<false><<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_keys(uint64_t *zbuf, int64_t npix, hipStream_t s) {
+    k_fill_keys<<<grid_for(npix, 2048), 256, 0, s>>>(zbuf, npix);
     return hipGetLastError();
 }
 
@@ -258,7 +281,7 @@ hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *swee
             pts, n, sweep, latest, motion, P, K,
             reinterpret_cast<unsigned long long *>(zbuf));
     if (depth || valid)
-        k_decode<<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
+        k_decode<false><<<grid_for(npix, 1024), 256, 0, s>>>(zbuf, npix, depth, valid);
     return hipGetLastError();
 }
 

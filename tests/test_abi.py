@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_status_strings(L):
     from paper_2601_01210_amd import binding
-    assert L.jbfd_abi_version() == 2
+    assert L.jbfd_abi_version() == 3
     for code in range(5):
         assert L.jbfd_status_string(code)
     assert L.jbfd_status_string(99) == b"unknown status"
@@ -72,6 +72,30 @@ def test_project_rejects_bad_arguments(L):
     assert L.jbfd_project(fake, 1, nanpose, C.byref(K), fake, None, None,
                           None) == JBFD_EINVAL
     assert b"pose" in L.jbfd_last_error()
+
+
+def test_recycled_projection_rejects_bad_arguments(L):
+    from paper_2601_01210_amd import binding
+    from paper_2601_01210_amd.binding import JBFD_EINVAL
+    binding.lib()   # argument types
+    pose = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    K = _K()
+    # the sparse outputs are required: the decode is what clears the keys
+    assert L.jbfd_project_recycled(fake, 10, pose, C.byref(K), fake, None, fake,
+                                   None) == JBFD_EINVAL
+    assert b"sparse" in L.jbfd_last_error()
+    assert L.jbfd_project_recycled(fake, 10, pose, C.byref(K), fake, fake, None,
+                                   None) == JBFD_EINVAL
+    # and the checks of jbfd_project, under the entry point's own name
+    assert L.jbfd_project_recycled(fake, -1, pose, C.byref(K), fake, fake, fake,
+                                   None) == JBFD_EINVAL
+    assert b"jbfd_project_recycled" in L.jbfd_last_error()
+    assert L.jbfd_project_recycled(fake, 1, pose, C.byref(K), None, fake, fake,
+                                   None) == JBFD_EINVAL
+    assert L.jbfd_zbuf_clear(None, 6, 8, None) == JBFD_EINVAL
+    assert L.jbfd_zbuf_clear(fake, 0, 8, None) == JBFD_EINVAL
+    assert L.jbfd_zbuf_clear(fake, 6, -1, None) == JBFD_EINVAL
 
 
 @pytest.mark.parametrize("radius,ss,sr", [(-1, 3.0, 12.0), (33, 3.0, 12.0),

@@ -117,6 +117,34 @@ def test_project_empty_and_keys_only(torch_dev):
     assert k[3, 4] == (np.float32(2.0).view(np.uint32).astype(np.uint64) << 32)
 
 
+@pytest.mark.parametrize("w,h", [(1920, 1080), (97, 61), (1, 1), (3, 7)])
+def test_project_recycled_frame_loop(torch_dev, w, h):
+    """jbfd_project_recycled over a loop of frames that reuses one key
+    buffer: each frame's depth and mask equal the oracle's bit for bit
+    (no key of an earlier frame survives), and the buffer holds only empty
+    keys after every frame. Odd sizes take the decode's per-pixel path."""
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import project, zbuf_clear
+    rng = np.random.default_rng(w * 7 + h)
+    pose = np.hstack([np.eye(3), np.zeros((3, 1))])
+    intr = (0.6 * w + 1.0, 0.6 * w + 1.0, w / 2.0, h / 2.0)
+    zbuf = torch.empty((h, w), dtype=torch.int64, device=dev)
+    zbuf_clear(zbuf)
+    empty = np.uint64(2 ** 64 - 1)
+    for frame, n in enumerate([5000, 17, 0, 40000, 3]):
+        pts = rng.normal(0, 1.0, size=(n, 3)).astype(np.float32)
+        pts[:, 2] = np.abs(pts[:, 2]) * 4 + 0.5
+        print(f"recycled frame {frame} {w}x{h} n={n}", flush=True)
+        _, depth, valid, _ = oracle.project(pts, pose, intr, w, h)
+        p = torch.from_numpy(pts).to(dev)
+        _, gd, gv = project(p, pose, intr, w, h, zbuf=zbuf, recycle=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(gd.cpu().numpy().view(np.uint32),
+                                      depth.view(np.uint32))
+        np.testing.assert_array_equal(gv.cpu().numpy(), valid)
+        assert np.all(zbuf.cpu().numpy().view(np.uint64) == empty)
+
+
 def test_project_scenes(torch_dev):
     torch, dev = torch_dev
     for name, f in [("small", S.small_view(S.seeded(1))),
