@@ -79,6 +79,7 @@ CASES = [
     (33, 520, 7, 0.5),        # nine groups: the group prefix spans batches
     (129, 257, 32, 0.05),
     (50, 60, 4, 0.0),         # nothing valid
+    (3, 32767, 32, 0.05),     # widest image: 4096 strips, 512 groups
 ]
 
 

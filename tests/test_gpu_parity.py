@@ -145,6 +145,24 @@ def test_project_recycled_frame_loop(torch_dev, w, h):
         assert np.all(zbuf.cpu().numpy().view(np.uint64) == empty)
 
 
+def test_project_largest_sides(torch_dev):
+    """Images of the largest side (32767) in either direction, with points
+    spread over the whole width or height: keys bit-exact."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(4)
+    pose = np.hstack([np.eye(3), np.zeros((3, 1))])
+    for w, h in [(32767, 3), (3, 32767)]:
+        n = 60000
+        z = rng.uniform(1.0, 10.0, n)
+        u = rng.uniform(-2, w + 2, n)
+        v = rng.uniform(-2, h + 2, n)
+        f = 50.0
+        pts = np.stack([(u - w / 2.0) * z / f, (v - h / 2.0) * z / f, z],
+                       axis=1).astype(np.float32)
+        print(f"projection {w}x{h}", flush=True)
+        _check_projection(torch, dev, pts, pose, (f, f, w / 2.0, h / 2.0), w, h)
+
+
 def test_project_scenes(torch_dev):
     torch, dev = torch_dev
     for name, f in [("small", S.small_view(S.seeded(1))),
@@ -209,6 +227,8 @@ FILTER_CASES = [
     (50, 66, 9, 0.03, 3.0, 2.0, 8),           # far colours: underflow-prone
     (129, 257, 16, 0.06, 5.0, 14.0, 7),       # radius at the template edge
     (129, 257, 17, 0.06, 5.0, 14.0, 7),       # first radius of the big table
+    (3, 32767, 32, 0.05, 8.0, 20.0, 5),       # widest image, largest radius
+    (32767, 2, 32, 0.05, 8.0, 20.0, 5),       # tallest image
 ]
 
 
