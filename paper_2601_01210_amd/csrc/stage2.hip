@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_restore_merge(
     float *__restrict__ D2, uint8_t *__restrict__ B2) {
     const int W1 = (W + 2) / 3;
     const int y = blockIdx.y, x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= W) return;
+    if (x >= W || y >= H) return;
     const int64_t p = (int64_t)y * W + x;
     const int64_t q = (int64_t)(y / 3) * W1 + x / 3;
     const uint8_t own_v = B[p], up_v = M1[q];
