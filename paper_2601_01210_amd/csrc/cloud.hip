@@ -189,11 +189,30 @@ __global__ __launch_bounds__(256) void k_cloud_write(
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) c12[3 * u + ch] = rgb[3 * (size_t)p + ch];
     }
-    // points of all earlier chunks
-    int64_t acc = 0;
-    for (int c = t; c < chunk; c += 256) acc += counts[c];
+    // points of all earlier chunks (in all at most H*W < 2^31): the counts
+    // of the first 2048 chunks are loaded together (Full-HD has 2025),
+    // later ones in further batches
+    int acc = 0;
+    {
+        int a[8];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        for (int u = 0; u < 8; ++u) {
+            const int c = 256 * u + t;
+            a[u] = counts[c < chunk ? c : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += 256 * u + t < chunk ? a[u] : 0;
+        for (int c0 = 8 * 256; c0 < chunk; c0 += 8 * 256) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = c0 + 256 * u + t;
+                a[u] = counts[c < chunk ? c : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += c0 + 256 * u + t < chunk ? a[u] : 0;
+        }
+    }
+    acc = wave_sum(acc);
     const int cnt = __builtin_popcount(bits);
     const int incl = wave_inclusive_scan(cnt);
     if (lane == 0) wacc[wid] = acc;
