@@ -291,7 +291,10 @@ __device__ __forceinline__ void list_scatter_unit(
         const int v = rl ? start[rl ? lane : 0][q] : 0;
         const int incl = wave_inclusive_scan(v);
         const int st = sbase[q] + incl - v;
-        if (rl) start[lane][q] = st;
+        // kept for step (7) less the row's samples left of the strip's first
+        // halo column, so that a sample's index there is this plus its own
+        // rank in the row
+        if (rl) start[lane][q] = st - popc128(mlo[lane], mhi[lane], 0, 8 * q);
         const int s = s_first + q;
         const int y = y_band + lane;
         if (s < n_strips) {
@@ -367,7 +370,8 @@ __device__ __forceinline__ void list_scatter_unit(
             uint32_t rg, b0;
             float nq2h;
             colour_fields(c01[u], c2[u], rg, b0, nq2h);
-            const uint64_t ml = mlo[row], mh = mhi[row];
+            // the sample's rank among the row's samples (columns left of it)
+            const int rank = popc128(mlo[row], mhi[row], 0, lc);
             const int4 sa = *reinterpret_cast<const int4 *>(&start[row][0]);
             const int4 sb = *reinterpret_cast<const int4 *>(&start[row][4]);
             const int st[kGroupStrips] = {sa.x, sa.y, sa.z, sa.w,
@@ -376,7 +380,7 @@ __device__ __forceinline__ void list_scatter_unit(
             for (int q = 0; q < kGroupStrips; ++q) {
                 // strips q of the group with 8q <= lc < 8q + 8 + 2r
                 if (q >= n_here || lc < 8 * q || lc >= 8 * q + 8 + 2 * r) continue;
-                const int64_t idx = (int64_t)st[q] + popc128(ml, mh, 8 * q, lc);
+                const int64_t idx = (int64_t)(st[q] + rank);
                 if (idx >= capacity) continue;
                 // words 0-3 are the same for every strip of this sample, so
                 // their (merged) store never waits on a rewritten register
