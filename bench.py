@@ -2,10 +2,11 @@
 
 Main line (``value``): one step = the whole hot path on one synthetic
 Full-HD viewpoint whose inputs are already resident in HBM, launched
-eagerly (the rate of the same steps replayed as HIP graphs is printed
-beside it): projection of
-the ~2e5 merged points of three staggered 32-beam sweeps (clear + project +
-decode), the per-strip sample lists, and the r = 15, sigma_s = 6,
+eagerly as one jbfd_project_densify call (the rate of the same steps
+replayed as HIP graphs is printed beside it): projection of the ~2e5
+merged points of three staggered 32-beam sweeps into a reused key buffer,
+the key decode fused with the count of the per-strip sample lists, the
+list scatter (which clears the keys again), and the r = 15, sigma_s = 6,
 sigma_r = 15 joint bilateral filter. Input and output buffers rotate over
 enough distinct copies (> 512 MB) that the 256 MB Infinity Cache cannot
 hold them. Printed beside it: per-kernel durations from HIP events on the
@@ -572,7 +573,8 @@ def main():
     import torch
 
     from paper_2601_01210_amd import (densify, densify_prepare,
-                                      densify_workspace, project, zbuf_clear)
+                                      densify_workspace, project, project_densify,
+                                      zbuf_clear)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -608,19 +610,24 @@ def main():
         zbuf_clear(b["zbuf"])
 
     def step(b, ev=None):
-        if ev is not None:
-            ev[0].record(stream)
+        if ev is None:
+            # one call: projection, key decode fused into the list build,
+            # filter (jbfd_project_densify)
+            project_densify(b["pts"], cam.pose, cam.intrinsics(), W, H, b["rgb"], r,
+                            ss, sr, b["zbuf"], b["ws"], depth=b["d"], valid=b["v"],
+                            out=b["out"], mask=b["m"])
+            return
+        # the same steps as separate calls, with HIP events between them for
+        # the per-stage durations (the filter kernel is the same)
+        ev[0].record(stream)
         project(b["pts"], cam.pose, cam.intrinsics(), W, H, zbuf=b["zbuf"],
                 depth=b["d"], valid=b["v"], recycle=True)
-        if ev is not None:
-            ev[1].record(stream)
+        ev[1].record(stream)
         densify_prepare(b["d"], b["v"], b["rgb"], r, b["ws"])
-        if ev is not None:
-            ev[2].record(stream)
+        ev[2].record(stream)
         densify(b["d"], b["v"], b["rgb"], r, ss, sr, out=b["out"],
                 mask=b["m"], ws=b["ws"], lists_ready=True)
-        if ev is not None:
-            ev[3].record(stream)
+        ev[3].record(stream)
 
     for k in range(args.warmup):
         step(sets[k % n_sets])
@@ -824,8 +831,8 @@ def main():
                    "radius": r, "sigma_s": ss, "sigma_r": sr,
                    "points": n_pts, "valid_pixels": n_valid,
                    "seed": args.seed, "buffer_sets": n_sets},
-        "step": "projection into a reused key buffer (the decode writes the "
-                "empty key back), sample lists, FP32 filter",
+        "step": "jbfd_project_densify: projection into a reused key buffer, "
+                "key decode fused into the sample-list build, FP32 filter",
         "kernel_ms": {"project": round(float(proj_ms.mean()), 4),
                       "sample_lists": round(float(list_ms.mean()), 4),
                       "k_jbf_fwd_f32": round(float(filt_ms.mean()), 4),

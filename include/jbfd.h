@@ -9,7 +9,9 @@
  *                      sparse depth image in its camera (Sec. 2), the
  *                      nearest point winning each pixel (z-buffer);
  *                      jbfd_project_recycled and jbfd_zbuf_clear do the same
- *                      for a frame loop that reuses its key buffer;
+ *                      for a frame loop that reuses its key buffer, and
+ *                      jbfd_project_densify runs both steps below in one
+ *                      call with the key decode fused into the list build;
  *   2. jbfd_densify  - RGB-guided joint bilateral filter over that sparse
  *                      depth image (Eq. 1-4, organised as Algorithm 1),
  *                      giving a dense depth image and a validity mask;
@@ -178,6 +180,28 @@ jbfd_status jbfd_project_recycled(const float *pts_xyz, int64_t n,
                                   const jbfd_intrinsics *K, uint64_t *zbuf,
                                   float *sparse_depth, uint8_t *sparse_valid,
                                   void *stream);
+
+/*
+ * jbfd_project_recycled followed by jbfd_densify with sample lists, in one
+ * call that fuses the decode of the key image with the counting pass of the
+ * list build (the decode reads each unit's halo keys itself, and the list
+ * scatter clears the keys once the lists are written). Results are those of
+ * the two calls made separately, bit for bit: sparse_depth / sparse_valid
+ * as jbfd_project_recycled (required), dense_depth / dense_valid as
+ * jbfd_densify with the same workspace (no aux). zbuf holds only empty keys
+ * on entry and is left so (as for jbfd_project_recycled). When ws cannot
+ * hold the lists' tables (see jbfd_densify_ws_bytes), the call projects with
+ * jbfd_project_recycled and the filter streams its inputs. Errors as
+ * jbfd_project and jbfd_densify; sizes come from K.
+ */
+jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
+                                 const double cam_from_world[12],
+                                 const jbfd_intrinsics *K, const uint8_t *rgb_hwc,
+                                 int32_t radius, float sigma_s, float sigma_r,
+                                 jbfd_precision prec, uint64_t *zbuf,
+                                 float *sparse_depth, uint8_t *sparse_valid,
+                                 float *dense_depth, uint8_t *dense_valid, void *ws,
+                                 size_t ws_bytes, void *stream);
 
 /* Set every key of an H x W key buffer (device) to the empty key
  * UINT64_MAX, for jbfd_project_recycled. */

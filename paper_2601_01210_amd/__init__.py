@@ -13,5 +13,5 @@ from .binding import (BatchView, JbfdError, Precision,  # noqa: F401
                       batch_upload, densify, densify_backward,
                       densify_prepare, densify_two_stage, densify_workspace,
                       densify_ws_bytes, library_path, motion_mask, pool3,
-                      project, project_motion, restore_merge,
+                      project, project_densify, project_motion, restore_merge,
                       two_stage_ws_bytes, zbuf_clear)

@@ -86,6 +86,10 @@ def lib():
         L.jbfd_project_recycled.argtypes = L.jbfd_project.argtypes
         L.jbfd_zbuf_clear.restype = C.c_int
         L.jbfd_zbuf_clear.argtypes = [vp, i32, i32, vp]
+        L.jbfd_project_densify.restype = C.c_int
+        L.jbfd_project_densify.argtypes = [vp, i64, C.POINTER(C.c_double),
+                                           C.POINTER(Intrinsics), vp, i32, f32, f32,
+                                           C.c_int, vp, vp, vp, vp, vp, vp, sz, vp]
         L.jbfd_densify.restype = C.c_int
         L.jbfd_densify.argtypes = [vp, vp, vp, i32, i32, i32, f32, f32,
                                    C.c_int, vp, vp, vp, vp, sz, C.c_uint32,
@@ -224,6 +228,44 @@ def project(points, pose, intrinsics: Sequence[float], width: int,
     _check(fn(_ptr(points), int(points.shape[0]), _pose_array(pose), C.byref(K),
               _ptr(zbuf), _ptr(depth), _ptr(valid), _stream(dev)))
     return zbuf, depth, valid
+
+
+def project_densify(points, pose, intrinsics: Sequence[float], width: int,
+                    height: int, rgb, radius: int, sigma_s: float, sigma_r: float,
+                    zbuf, ws, precision: Precision = Precision.FP32, depth=None,
+                    valid=None, out=None, mask=None):
+    """Projection and filter in one call (jbfd_project_densify): the decode
+    of the key image is fused into the list build. ``zbuf`` holds only empty
+    keys (see :func:`zbuf_clear`) and is left so; ``ws`` is a list workspace
+    (:func:`densify_workspace`). Returns (depth, valid, out, mask)."""
+    torch = _torch()
+    _need(points, torch.float32, None, "points")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (N, 3)")
+    dev = points.device
+    h, w = int(height), int(width)
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    _need(zbuf, torch.int64, (h, w), "zbuf")
+    _need(ws, torch.uint8, None, "ws")
+    if depth is None:
+        depth = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if valid is None:
+        valid = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if mask is None:
+        mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    for t, dt, nm in ((depth, torch.float32, "depth"), (valid, torch.uint8, "valid"),
+                      (out, torch.float32, "out"), (mask, torch.uint8, "mask")):
+        _need(t, dt, (h, w), nm)
+    K = Intrinsics(float(intrinsics[0]), float(intrinsics[1]),
+                   float(intrinsics[2]), float(intrinsics[3]), w, h)
+    _check(lib().jbfd_project_densify(
+        _ptr(points), int(points.shape[0]), _pose_array(pose), C.byref(K), _ptr(rgb),
+        int(radius), float(sigma_s), float(sigma_r), int(precision), _ptr(zbuf),
+        _ptr(depth), _ptr(valid), _ptr(out), _ptr(mask), _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return depth, valid, out, mask
 
 
 def zbuf_clear(zbuf):

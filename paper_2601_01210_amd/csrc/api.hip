@@ -143,6 +143,38 @@ jbfd_status jbfd_project_recycled(const float *pts_xyz, int64_t n,
                           zbuf, sparse_depth, sparse_valid, true, stream);
 }
 
+jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
+                                 const double cam_from_world[12],
+                                 const jbfd_intrinsics *K, const uint8_t *rgb_hwc,
+                                 int32_t radius, float sigma_s, float sigma_r,
+                                 jbfd_precision prec, uint64_t *zbuf,
+                                 float *sparse_depth, uint8_t *sparse_valid,
+                                 float *dense_depth, uint8_t *dense_valid, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    const char *name = "jbfd_project_densify";
+    jbfd_status st = check_project(name, pts_xyz, n, cam_from_world, K, zbuf);
+    if (st != JBFD_OK) return st;
+    if (!rgb_hwc || !sparse_depth || !sparse_valid || !dense_depth || !dense_valid)
+        return fail(JBFD_EINVAL, "%s: null buffer", name);
+    st = check_filter(radius, sigma_s, sigma_r);
+    if (st != JBFD_OK) return st;
+    if (prec != JBFD_FP32 && prec != JBFD_FP16_RANGE)
+        return fail(JBFD_EINVAL, "%s: unknown precision %d", name, (int)prec);
+    if (ws && ((uintptr_t)ws & 255))
+        return fail(JBFD_EINVAL, "%s: workspace not 256-byte aligned", name);
+    if (!ws) ws_bytes = 0;
+    jbfd::Pose P;
+    for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
+    jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
+    jbfd::FilterParams fp{radius, log2_half_inv_var(sigma_r), log2_half_inv_var(sigma_s)};
+    const hipError_t e = jbfd::launch_project_densify(
+        pts_xyz, n, P, I, rgb_hwc, fp, prec, zbuf, sparse_depth, sparse_valid,
+        dense_depth, dense_valid, ws, ws_bytes, (hipStream_t)stream);
+    if (e == hipErrorNotSupported)
+        return fail(JBFD_EUNSUPPORTED, "%s: precision not built", name);
+    return hip_status(e, name);
+}
+
 jbfd_status jbfd_zbuf_clear(uint64_t *zbuf, int32_t H, int32_t W, void *stream) {
     if (!zbuf) return fail(JBFD_EINVAL, "jbfd_zbuf_clear: null zbuf");
     const jbfd_status st = check_image(H, W);

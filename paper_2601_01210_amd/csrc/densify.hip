@@ -102,29 +102,25 @@ __device__ __forceinline__ void row_ballots(int H, int W, int c0, int y_first,
     }
 }
 
-// Records per (strip, band): workgroup (group g, band b); wave w ballots a
-// quarter of the band's rows; lanes 0..7 count the rows' samples in the
-// halo of strip 8g + lane. (The unit functions are forced inline: called out
-// of line, their uniform arguments and pointers would live in vector
-// registers and their loads would lose their scalar bases.)
-__device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, int H, int W,
-                                       int r, int n_strips, int n_bands,
-                                       int *__restrict__ bandcnt,
-                                       int *__restrict__ grpcnt, int g, int band) {
+// Records per (strip, band) from the row masks of the unit (group g, band
+// b): lanes 0..7 of each wave count its rows' samples in the halo of strip
+// 8g + lane; wave 0 sums the four waves and the group. (The unit functions
+// are forced inline: called out of line, their uniform arguments and
+// pointers would live in vector registers and their loads would lose their
+// scalar bases.)
+template <int NROWS>
+__device__ __forceinline__ void count_strips(const uint64_t (&lo)[NROWS],
+                                             const uint64_t (&hi)[NROWS], int r,
+                                             int n_strips, int n_bands,
+                                             int *__restrict__ bandcnt,
+                                             int *__restrict__ grpcnt, int g, int band) {
     __shared__ int part[4][kGroupStrips];
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int c0 = 64 * g - r;
-    constexpr int kRowsPerWave = kBandRows / 4;
-    const int y_first = band * kBandRows + wid * kRowsPerWave;
-    uint8_t va[kRowsPerWave], vb[kRowsPerWave];
-    group_row_bytes<kRowsPerWave>(B, H, W, c0, y_first, va, vb);
-    uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
-    row_ballots<kRowsPerWave>(H, W, c0, y_first, va, vb, lo, hi);
     int acc = 0;
     if (lane < kGroupStrips) {
 #pragma unroll
-        for (int k = 0; k < kRowsPerWave; ++k)
+        for (int k = 0; k < NROWS; ++k)
             acc += popc128(lo[k], hi[k], 8 * lane, 8 * lane + 8 + 2 * r);
         part[wid][lane] = acc;
     }
@@ -142,6 +138,23 @@ __device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, i
     }
 }
 
+// Records per (strip, band): workgroup (group g, band b); wave w ballots a
+// quarter of the band's rows from the validity bytes.
+__device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, int H, int W,
+                                       int r, int n_strips, int n_bands,
+                                       int *__restrict__ bandcnt,
+                                       int *__restrict__ grpcnt, int g, int band) {
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = 64 * g - r;
+    constexpr int kRowsPerWave = kBandRows / 4;
+    const int y_first = band * kBandRows + wid * kRowsPerWave;
+    uint8_t va[kRowsPerWave], vb[kRowsPerWave];
+    group_row_bytes<kRowsPerWave>(B, H, W, c0, y_first, va, vb);
+    uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
+    row_ballots<kRowsPerWave>(H, W, c0, y_first, va, vb, lo, hi);
+    count_strips<kRowsPerWave>(lo, hi, r, n_strips, n_bands, bandcnt, grpcnt, g, band);
+}
+
 __global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ B,
                                                     int H, int W, int r, int n_strips,
                                                     int n_bands,
@@ -149,6 +162,60 @@ __global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ 
                                                     int *__restrict__ grpcnt) {
     list_count_unit(B, H, W, r, n_strips, n_bands, bandcnt, grpcnt, blockIdx.x,
                     blockIdx.y);
+}
+
+// Decode and count in one pass, for a projection straight into the sample
+// lists (jbfd_project_densify). Unit (group g, band b) reads the keys of the
+// band's rows over the group's 128 halo columns, writes depth and validity
+// of its own 64 columns [64g, 64g + 64) (lane l decodes column
+// 64g + ((l - r) mod 64) of each row, from the key it loaded in the first
+// or the second half; r <= 32 < 64) and counts each strip's samples as
+// k_list_count does. Keys are only read here (the list scatter clears them
+// afterwards), so a unit may read its neighbours' columns.
+__global__ __launch_bounds__(256) void k_decode_count(const uint64_t *__restrict__ keys,
+                                                      int H, int W, int r, int n_strips,
+                                                      int n_bands, float *__restrict__ D,
+                                                      uint8_t *__restrict__ B,
+                                                      int *__restrict__ bandcnt,
+                                                      int *__restrict__ grpcnt) {
+    const int g = blockIdx.x, band = blockIdx.y;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int c0 = 64 * g - r;
+    constexpr int kRowsPerWave = kBandRows / 4;
+    const int y_first = band * kBandRows + wid * kRowsPerWave;
+    const int xa = c0 + lane, xb = c0 + 64 + lane;
+    const int xa_c = min(max(xa, 0), W - 1), xb_c = min(max(xb, 0), W - 1);
+    uint64_t ka[kRowsPerWave], kb[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {   // all loads in flight together
+        const uint64_t *row = keys + (int64_t)min(y_first + k, H - 1) * W;
+        ka[k] = row[xa_c];
+        kb[k] = row[xb_c];
+    }
+    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
+    uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+        const bool iny = y_first + k < H;
+        lo[k] = __builtin_amdgcn_ballot_w64(ina && iny && ka[k] != kEmptyKey);
+        hi[k] = __builtin_amdgcn_ballot_w64(inb && iny && kb[k] != kEmptyKey);
+    }
+    const bool own_a = lane >= r;
+    const int xo = own_a ? xa : xb;   // in [64g, 64g + 64)
+    if (xo < W) {
+#pragma unroll
+        for (int k = 0; k < kRowsPerWave; ++k) {
+            const int y = y_first + k;
+            if (y >= H) break;
+            const uint64_t key = own_a ? ka[k] : kb[k];
+            const bool hit = key != kEmptyKey;
+            const int64_t p = (int64_t)y * W + xo;
+            D[p] = hit ? __uint_as_float((uint32_t)(key >> 32)) : 0.0f;
+            B[p] = (uint8_t)hit;
+        }
+    }
+    count_strips<kRowsPerWave>(lo, hi, r, n_strips, n_bands, bandcnt, grpcnt, g, band);
 }
 
 // Offsets and records of the group's strips over one band (see the file
@@ -399,9 +466,23 @@ __global__ __launch_bounds__(256) void k_list_scatter(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
     int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
-    int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs) {
+    int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs,
+    uint64_t *__restrict__ reset_keys) {
     list_scatter_unit(D, B, rgb, H, W, r, n_strips, n_bands, bandcnt, grpcnt, rowoff,
                       capacity, recs, blockIdx.x, blockIdx.y);
+    if (reset_keys) {
+        // the unit's own columns [64g, 64g + 64) of its band: no other unit
+        // reads them once the decode that precedes this kernel has finished
+        const int x = 64 * (int)blockIdx.x + (int)(threadIdx.x & 63);
+        const int y0 = (int)blockIdx.y * kBandRows;
+        if (x < W) {
+#pragma unroll
+            for (int k = (int)(threadIdx.x >> 6); k < kBandRows; k += 4) {
+                const int y = y0 + k;
+                if (y < H) reset_keys[(int64_t)y * W + x] = kEmptyKey;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -594,7 +675,7 @@ hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
                                       v.bandcnt, v.grpcnt);
     k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, radius, L.n_strips,
                                         L.n_bands, v.bandcnt, v.grpcnt, v.rowoff,
-                                        v.capacity, v.recs);
+                                        v.capacity, v.recs, nullptr);
     return hipGetLastError();
 }
 
@@ -635,6 +716,36 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                 D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, nullptr);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_project_densify(const float *pts, int64_t n, const Pose &pose,
+                                  const Intr &K, const uint8_t *rgb,
+                                  const FilterParams &fp, jbfd_precision prec,
+                                  uint64_t *zbuf, float *D, uint8_t *B, float *out,
+                                  uint8_t *mask, void *ws, size_t ws_bytes,
+                                  hipStream_t s) {
+    const int H = K.h, W = K.w;
+    const ListLayout L = list_layout(H, W);
+    ListViews v;
+    if (!lists_possible(H, W, fp.radius) || !list_views(ws, ws_bytes, L, v)) {
+        // no lists: the recycling projection, then the streaming filter
+        hipError_t e = launch_project(pts, n, pose, K, zbuf, D, B, true, s);
+        if (e != hipSuccess) return e;
+        return launch_densify(D, B, rgb, H, W, fp, prec, out, mask, nullptr, ws,
+                              ws_bytes, false, s);
+    }
+    hipError_t e = launch_project_keys(pts, n, pose, K, zbuf, s);
+    if (e != hipSuccess) return e;
+    const dim3 grid(L.n_groups, L.n_bands);
+    k_decode_count<<<grid, 256, 0, s>>>(zbuf, H, W, fp.radius, L.n_strips, L.n_bands,
+                                        D, B, v.bandcnt, v.grpcnt);
+    k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, fp.radius, L.n_strips,
+                                        L.n_bands, v.bandcnt, v.grpcnt, v.rowoff,
+                                        v.capacity, v.recs, zbuf);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_densify(D, B, rgb, H, W, fp, prec, out, mask, nullptr, ws, ws_bytes,
+                          true, s);
 }
 
 }  // namespace jbfd

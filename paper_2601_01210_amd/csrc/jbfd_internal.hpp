@@ -34,6 +34,15 @@ hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
                           const Intr &K, uint64_t *zbuf, float *depth,
                           uint8_t *valid, bool recycle, hipStream_t s);
 hipError_t launch_fill_keys(uint64_t *zbuf, int64_t npix, hipStream_t s);
+// only the atomics of the projection (no clear, no decode)
+hipError_t launch_project_keys(const float *pts, int64_t n, const Pose &pose,
+                               const Intr &K, uint64_t *zbuf, hipStream_t s);
+hipError_t launch_project_densify(const float *pts, int64_t n, const Pose &pose,
+                                  const Intr &K, const uint8_t *rgb,
+                                  const FilterParams &fp, jbfd_precision prec,
+                                  uint64_t *zbuf, float *D, uint8_t *B, float *out,
+                                  uint8_t *mask, void *ws, size_t ws_bytes,
+                                  hipStream_t s);
 
 hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                           int32_t H, int32_t W, const FilterParams &fp,

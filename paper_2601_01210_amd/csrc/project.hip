@@ -265,6 +265,14 @@ hipError_t launch_project(const float *pts, int64_t n, const Pose &pose,
     return hipGetLastError();
 }
 
+hipError_t launch_project_keys(const float *pts, int64_t n, const Pose &pose,
+                               const Intr &K, uint64_t *zbuf, hipStream_t s) {
+    if (n > 0)
+        k_project<<<grid_for(n, 256), 256, 0, s>>>(
+            pts, n, pose, K, reinterpret_cast<unsigned long long *>(zbuf));
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_keys(uint64_t *zbuf, int64_t npix, hipStream_t s) {
     k_fill_keys<<<grid_for(npix, 2048), 256, 0, s>>>(zbuf, npix);
     return hipGetLastError();

@@ -94,6 +94,23 @@ def test_recycled_projection_rejects_bad_arguments(L):
     assert L.jbfd_project_recycled(fake, 1, pose, C.byref(K), None, fake, fake,
                                    None) == JBFD_EINVAL
     assert L.jbfd_zbuf_clear(None, 6, 8, None) == JBFD_EINVAL
+    # the fused projection + filter: the checks of both calls
+    pd = L.jbfd_project_densify
+    pd.restype = C.c_int
+    args = lambda **o: [o.get("pts", fake), o.get("n", 10), pose, C.byref(o.get("K", K)),
+                        o.get("rgb", fake), o.get("r", 5), o.get("ss", C.c_float(3.0)),
+                        o.get("sr", C.c_float(12.0)), o.get("prec", 0),
+                        o.get("zbuf", fake), o.get("d", fake), o.get("v", fake),
+                        o.get("out", fake), o.get("m", fake), o.get("ws", None),
+                        C.c_size_t(0), None]
+    for bad, msg in ((dict(zbuf=None), b"zbuf"), (dict(rgb=None), b"null buffer"),
+                     (dict(d=None), b"null buffer"), (dict(m=None), b"null buffer"),
+                     (dict(r=33), b"radius"), (dict(prec=7), b"precision"),
+                     (dict(n=-1), b"n = -1"), (dict(K=_K(0, 6)), b"image size"),
+                     (dict(ss=C.c_float(0.0)), b"sigma_s"),
+                     (dict(ws=C.c_void_p(0x1010)), b"aligned")):
+        assert pd(*args(**bad)) == JBFD_EINVAL, bad
+        assert msg in L.jbfd_last_error(), (bad, L.jbfd_last_error())
     assert L.jbfd_zbuf_clear(fake, 0, 8, None) == JBFD_EINVAL
     assert L.jbfd_zbuf_clear(fake, 6, -1, None) == JBFD_EINVAL
 

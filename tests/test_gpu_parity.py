@@ -145,6 +145,65 @@ def test_project_recycled_frame_loop(torch_dev, w, h):
         assert np.all(zbuf.cpu().numpy().view(np.uint64) == empty)
 
 
+FUSED_CASES = [
+    # w, h, r, precision
+    (1920, 1080, 15, "FP32"),
+    (97, 61, 5, "FP32"),
+    (130, 3, 32, "FP32"),
+    (9, 70, 15, "FP16_RANGE"),     # narrower than a group: halo past both edges
+    (200, 150, 0, "FP32"),
+]
+
+
+@pytest.mark.parametrize("case", FUSED_CASES, ids=[f"{c[0]}x{c[1]}r{c[2]}{c[3]}" for c in FUSED_CASES])
+def test_project_densify_equals_separate_calls(torch_dev, case):
+    """jbfd_project_densify over a frame loop equals jbfd_project_recycled +
+    jbfd_densify_prepare + jbfd_densify with the same workspace, bit for bit
+    (sparse and dense outputs), and leaves the key buffer empty; with a
+    workspace too small for the lists' tables it equals the streaming
+    filter."""
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import (Precision, densify, densify_prepare,
+                                      densify_workspace, project, project_densify,
+                                      zbuf_clear)
+    w, h, r, pname = case
+    prec = Precision[pname]
+    rng = np.random.default_rng(w + 13 * h + r)
+    pose = np.hstack([np.eye(3), np.zeros((3, 1))])
+    intr = (0.7 * w + 1.0, 0.7 * w + 1.0, w / 2.0, h / 2.0)
+    rgb = torch.from_numpy(rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8)).to(dev)
+    za = zbuf_clear(torch.empty((h, w), dtype=torch.int64, device=dev))
+    zb = zbuf_clear(torch.empty((h, w), dtype=torch.int64, device=dev))
+    empty = np.uint64(2 ** 64 - 1)
+    for frame, n in enumerate([int(0.08 * w * h) + 5, 0, int(0.02 * w * h) + 1]):
+        pts = rng.normal(0, 1.0, size=(n, 3)).astype(np.float32)
+        pts[:, 2] = np.abs(pts[:, 2]) * 4 + 0.5
+        p = torch.from_numpy(pts).to(dev)
+        print(f"fused {w}x{h} r={r} {pname} frame {frame} n={n}", flush=True)
+        for ws_kind in ("lists", "small"):
+            nmax = max(n, 1)
+            ws = densify_workspace(h, w, r, nmax, device=dev)
+            if ws_kind == "small":
+                ws = torch.empty(256, dtype=torch.uint8, device=dev)
+            d1, v1, o1, m1 = project_densify(p, pose, intr, w, h, rgb, r, 3.0, 12.0,
+                                             za, ws, prec)
+            ws2 = torch.empty_like(ws)
+            _, d2, v2 = project(p, pose, intr, w, h, zbuf=zb, recycle=True)
+            if ws_kind == "lists":
+                densify_prepare(d2, v2, rgb, r, ws2)
+                o2, m2 = densify(d2, v2, rgb, r, 3.0, 12.0, prec, ws=ws2,
+                                 lists_ready=True)
+            else:
+                o2, m2 = densify(d2, v2, rgb, r, 3.0, 12.0, prec, ws=None)
+            torch.cuda.synchronize()
+            assert torch.equal(d1.view(torch.int32), d2.view(torch.int32))
+            assert torch.equal(v1, v2)
+            assert torch.equal(m1, m2)
+            assert torch.equal(o1.view(torch.int32), o2.view(torch.int32)), ws_kind
+            assert np.all(za.cpu().numpy().view(np.uint64) == empty)
+            assert np.all(zb.cpu().numpy().view(np.uint64) == empty)
+
+
 def test_project_largest_sides(torch_dev):
     """Images of the largest side (32767) in either direction, with points
     spread over the whole width or height: keys bit-exact."""
