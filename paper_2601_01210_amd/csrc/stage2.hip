@@ -8,11 +8,12 @@
 //   k_restore_merge  one thread per pixel: the original depth where the
 //                    pixel holds a sample, else the first pass's output of
 //                    its cell (x/3, y/3) where that is valid;
-//   k_jbf_dense<R,T> the joint bilateral filter (Eq. 1-4) for inputs where
-//                    most pixels hold a sample and the radius is small: one
-//                    thread per output pixel loops over every tap of its
-//                    (2R+1)^2 window, read from a T x T tile plus halo staged
-//                    in LDS (T = 16, or 8 on small images). After pooling and
+//   k_jbf_dense<R,T,RPT> the joint bilateral filter (Eq. 1-4) for inputs
+//                    where most pixels hold a sample and the radius is small:
+//                    one thread per RPT output pixels loops over every tap of
+//                    their (2R+1)^2 windows, read from a tile plus halo staged
+//                    in LDS (16 x 32 pixels with two per thread, or 8 x 8 on
+//                    small images). After pooling and
 //                    restoring, nearly every window tap is valid, so a
 //                    wave-uniform walk over sample lists (the sparse kernel)
 //                    would spend most of its lanes outside the small windows.
@@ -103,32 +104,63 @@ __global__ __launch_bounds__(256) void k_restore_merge(
     B2[p] = (uint8_t)(own || up);
 }
 
-// Filter of one T x T tile with one thread per pixel (see the file comment);
-// T = 16, or 8 for images too small to give every CU several 16x16 tiles.
-template <int R, int T>
+// Exact pass of one pixel whose weights are all tiny (far colours or tiny
+// sigma_s): running shift, exact unclamped spatial exponents; row0 is the
+// tile row of the window's top edge.
+template <int R, int EX>
+__device__ __forceinline__ void dense_exact(const uint4 *tile, int row0, int lx,
+                                            uint32_t prg, uint32_t pb0, float p2,
+                                            const FilterParams &fp, float &num,
+                                            float &den) {
+    const float kr2 = 2.0f * fp.kr;
+    float M = kShiftInit - fp.kr * p2, n2 = 0.0f, d2 = 0.0f;
+    for (int dy = -R; dy <= R; ++dy) {
+        for (int dx = -R; dx <= R; ++dx) {
+            const uint4 q = tile[(row0 + R + dy) * EX + lx + R + dx];
+            if ((q.y >> 16) == 0u) continue;
+            const float tq = dot2h(prg, q.x, dot2h(pb0, q.y, __uint_as_float(q.w)));
+            consume1(tq, -fp.ks * (float)(dx * dx + dy * dy), __uint_as_float(q.z),
+                     kr2, M, n2, d2);
+        }
+    }
+    num = n2;
+    den = d2;
+}
+
+// Filter of one T x (RPT T) tile (see the file comment): T x T threads, each
+// for RPT vertically adjacent pixels. With RPT = 2 a thread reads each of
+// the 2R + 2 window rows of its pixel pair from LDS once and applies it to
+// both pixels, so the tile reads per pixel drop from (2R+1)^2 to
+// (2R+2)(2R+1)/2; each pixel still takes its taps row by row, left to
+// right. T = 16 with RPT = 2 on large images, T = 8 with RPT = 1 on images
+// too small to give every CU several workgroups.
+template <int R, int T, int RPT>
 __global__ __launch_bounds__(T * T) void k_jbf_dense(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
     int tiles_x, int n_tiles, int n_pad, float *__restrict__ out,
     uint8_t *__restrict__ mask) {
-    constexpr int E = T + 2 * R;              // tile edge with halo
+    static_assert(RPT == 1 || RPT == 2, "one or two rows per thread");
+    constexpr int EX = T + 2 * R;             // tile width with halo
+    constexpr int EY = RPT * T + 2 * R;       // tile height with halo
+    constexpr int NE = EX * EY;
     constexpr int NT = T * T;                 // threads
-    __shared__ uint4 tile[E * E + 1];
+    __shared__ uint4 tile[NE + 1];
     const int t = xcd_tile(blockIdx.x, n_pad);
     if (t >= n_tiles) return;                 // whole workgroup leaves together
-    const int ty0 = (t / tiles_x) * T, tx0 = (t % tiles_x) * T;
+    const int ty0 = (t / tiles_x) * (RPT * T), tx0 = (t % tiles_x) * T;
 
     // stage the tile and its halo: invalid and out-of-image pixels get a
     // zero depth and a zero valid flag. Every element's loads come from a
     // clamped address and are issued before any is used; elements past the
     // tile store into one spare record.
-    constexpr int NIT = (E * E + NT - 1) / NT;
+    constexpr int NIT = (NE + NT - 1) / NT;
     uint8_t cr[NIT][3], cv[NIT];
     float cd[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int e = min((int)threadIdx.x + NT * it, E * E - 1);
-        const int ly = e / E, lx = e - ly * E;
+        const int e = min((int)threadIdx.x + NT * it, NE - 1);
+        const int ly = e / EX, lx = e - ly * EX;
         const int y = min(max(ty0 - R + ly, 0), H - 1);
         const int x = min(max(tx0 - R + lx, 0), W - 1);
         const int64_t p = (int64_t)y * W + x;
@@ -141,9 +173,9 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int e = (int)threadIdx.x + NT * it;
-        const int ly = e / E, lx = e - ly * E;
+        const int ly = e / EX, lx = e - ly * EX;
         const int y = ty0 - R + ly, x = tx0 - R + lx;
-        const bool in = e < E * E && y >= 0 && y < H && x >= 0 && x < W;
+        const bool in = e < NE && y >= 0 && y < H && x >= 0 && x < W;
         uint32_t rg, b0;
         float nq2h;
         colour_fields((uint32_t)cr[it][0] | ((uint32_t)cr[it][1] << 8), cr[it][2],
@@ -154,18 +186,25 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
                                           __float_as_uint(v ? cd[it] : 0.0f),
                                           __float_as_uint(nq2h))
                              : make_uint4(0u, 0u, 0u, 0u);
-        tile[e < E * E ? e : E * E] = rec;
+        tile[e < NE ? e : NE] = rec;
     }
     __syncthreads();
 
-    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
-    const int px = tx0 + lx, py = ty0 + ly;
+    const int lx = threadIdx.x % T, row0 = RPT * (int)(threadIdx.x / T);
+    const int px = tx0 + lx, py = ty0 + row0;
     if (px >= W || py >= H) return;           // no barrier follows
-    const uint4 me = tile[(ly + R) * E + lx + R];
-    const uint32_t prg = me.x, pb0 = me.y & 0xFFFFu;   // (b, 0) for the dot
-    const float p2 = -2.0f * __uint_as_float(me.w);
+    const bool has1 = RPT == 2 && py + 1 < H;
+    uint32_t prg[RPT], pb0[RPT];
+    float p2[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const uint4 me = tile[(row0 + j + R) * EX + lx + R];
+        prg[j] = me.x;
+        pb0[j] = me.y & 0xFFFFu;                 // (b, 0) for the dot
+        p2[j] = -2.0f * __uint_as_float(me.w);
+    }
     const float kr2 = 2.0f * fp.kr;
-    const float Mfast = -fp.kr * p2;
+    const Pass1Exp p1a(kr2, -fp.kr * p2[0]), p1b(kr2, -fp.kr * p2[RPT - 1]);
 
     // spatial exponents of the distinct squared distances, clamped as in
     // the sparse kernel's table
@@ -174,42 +213,42 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
     for (int s = 0; s <= 2 * R * R; ++s)
         gs[s] = fmaxf(-fp.ks * (float)s, kClampExp);
 
-    float num = 0.0f, den = 0.0f;
-    const Pass1Exp p1(kr2, Mfast);
+    float num[RPT], den[RPT];
 #pragma unroll
-    for (int dy = -R; dy <= R; ++dy) {
+    for (int j = 0; j < RPT; ++j) num[j] = den[j] = 0.0f;
+    // window row k of the pixel group: row k - R of pixel 0, row k - R - 1
+    // of pixel 1
+#pragma unroll
+    for (int k = 0; k < 2 * R + RPT; ++k) {
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
-            const uint4 q = tile[(ly + R + dy) * E + lx + R + dx];
-            const float tq = dot2h(prg, q.x, dot2h(pb0, q.y, __uint_as_float(q.w)));
-            const float a = p1(tq, gs[dx * dx + dy * dy]);
-            const float w = __builtin_amdgcn_exp2f(a);
+            const uint4 q = tile[(row0 + k) * EX + lx + R + dx];
             const _Float16 vf = __builtin_bit_cast(h2, q.y)[1];
-            num = __builtin_fmaf(w, __uint_as_float(q.z), num);
-            den = __builtin_fmaf(w, (float)vf, den);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int dy = k - R - j;
+                if (dy < -R || dy > R) continue;
+                const float tq =
+                    dot2h(prg[j], q.x, dot2h(pb0[j], q.y, __uint_as_float(q.w)));
+                const float a = (j == 0 ? p1a : p1b)(tq, gs[dx * dx + dy * dy]);
+                const float w = __builtin_amdgcn_exp2f(a);
+                num[j] = __builtin_fmaf(w, __uint_as_float(q.z), num[j]);
+                den[j] = __builtin_fmaf(w, (float)vf, den[j]);
+            }
         }
     }
 
-    // exact pass for lanes whose weights are all tiny (far colours or tiny
-    // sigma_s): running shift, exact unclamped spatial exponents
-    if (den > 0.0f && den < kWeakBelow) {
-        float M = kShiftInit - fp.kr * p2, n2 = 0.0f, d2 = 0.0f;
-        for (int dy = -R; dy <= R; ++dy) {
-            for (int dx = -R; dx <= R; ++dx) {
-                const uint4 q = tile[(ly + R + dy) * E + lx + R + dx];
-                if ((q.y >> 16) == 0u) continue;
-                const float tq = dot2h(prg, q.x, dot2h(pb0, q.y, __uint_as_float(q.w)));
-                consume1(tq, -fp.ks * (float)(dx * dx + dy * dy),
-                         __uint_as_float(q.z), kr2, M, n2, d2);
-            }
-        }
-        num = n2;
-        den = d2;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        if (j == 1 && !has1) break;
+        if (den[j] > 0.0f && den[j] < kWeakBelow)
+            dense_exact<R, EX>(tile, row0 + j, lx, prg[j], pb0[j], p2[j], fp, num[j],
+                               den[j]);
+        const int64_t p = (int64_t)(py + j) * W + px;
+        const bool ok = den[j] > 0.0f;
+        out[p] = ok ? num[j] / den[j] : 0.0f;
+        mask[p] = (uint8_t)ok;
     }
-    const int64_t p = (int64_t)py * W + px;
-    const bool ok = den > 0.0f;
-    out[p] = ok ? num / den : 0.0f;
-    mask[p] = (uint8_t)ok;
 }
 
 hipError_t launch_pool3(const float *D, const uint8_t *B, const uint8_t *rgb,
@@ -233,23 +272,24 @@ hipError_t launch_densify_dense(const float *D, const uint8_t *B,
                                 const uint8_t *rgb, int32_t H, int32_t W,
                                 const FilterParams &fp, float *out,
                                 uint8_t *mask, hipStream_t s) {
-    // 16x16 tiles when there are at least eight per CU, else 8x8 tiles
-    const bool big = (int64_t)((W + 15) / 16) * ((H + 15) / 16) >= 2048;
-    const int T = big ? 16 : 8;
+    // 16x32 tiles (two rows per thread) when there are at least eight per
+    // CU, else 8x8 tiles (one row per thread)
+    const bool big = (int64_t)((W + 15) / 16) * ((H + 31) / 32) >= 2048;
+    const int T = big ? 16 : 8, TY = big ? 32 : 8;
     const int tiles_x = (W + T - 1) / T;
-    const int tiles_y = (H + T - 1) / T;
+    const int tiles_y = (H + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
     const int n_pad = (n_tiles + 7) & ~7;
 #define JBFD_DENSE_CASE(RR)                                                    \
     case RR:                                                                   \
         if (big)                                                               \
-            k_jbf_dense<RR, 16><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp,     \
-                                                     tiles_x, n_tiles, n_pad,  \
-                                                     out, mask);               \
+            k_jbf_dense<RR, 16, 2><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp,  \
+                                                        tiles_x, n_tiles,      \
+                                                        n_pad, out, mask);     \
         else                                                                   \
-            k_jbf_dense<RR, 8><<<n_pad, 64, 0, s>>>(D, B, rgb, H, W, fp,       \
-                                                   tiles_x, n_tiles, n_pad,    \
-                                                   out, mask);                 \
+            k_jbf_dense<RR, 8, 1><<<n_pad, 64, 0, s>>>(D, B, rgb, H, W, fp,    \
+                                                      tiles_x, n_tiles, n_pad, \
+                                                      out, mask);              \
         break;
     switch (fp.radius) {
         JBFD_DENSE_CASE(0) JBFD_DENSE_CASE(1) JBFD_DENSE_CASE(2)

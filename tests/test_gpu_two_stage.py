@@ -73,9 +73,16 @@ DENSE_CASES = [
     (50, 66, 3, 0.9, 0.25, 0.25),       # tiny widths: exact pass
     (1, 37, 2, 0.5, 1.0, 12.0),
     (17, 1, 4, 0.5, 1.0, 12.0),
-    # images with at least 2048 16x16 tiles take the 16x16-tile kernel
+    # below 2048 tiles of 16x32 the 8x8-tile kernel runs
     (1000, 600, 4, 0.5, 2.0, 15.0),
     (800, 700, 1, 0.9, 1.0, 12.0),
+    # at least 2048 16x32 tiles: the kernel with two pixel rows per thread,
+    # ragged in both directions (an odd last row leaves its thread's second
+    # pixel outside the image)
+    (1101, 1000, 4, 0.5, 2.0, 15.0),
+    (1090, 1030, 2, 0.9, 1.0, 12.0),
+    (1057, 1040, 0, 0.9, 1.0, 12.0),
+    (1090, 1030, 3, 0.9, 0.25, 0.25),   # tiny widths: exact pass
 ]
 
 
