@@ -135,10 +135,15 @@ hipError_t launch_restore_merge(const float *D, const uint8_t *B,
                                 const float *O1, const uint8_t *M1, int32_t H,
                                 int32_t W, float *D2, uint8_t *B2,
                                 hipStream_t s);
+// O1, M1: NULL, or the first pass of the two-stage filter (a third of the
+// resolution in each dimension): the kernel then filters the restored image
+// (own sample, else the cell's first-pass output) without storing it.
 hipError_t launch_densify_dense(const float *D, const uint8_t *B,
                                 const uint8_t *rgb, int32_t H, int32_t W,
                                 const FilterParams &fp, float *out,
-                                uint8_t *mask, hipStream_t s);
+                                uint8_t *mask, hipStream_t s,
+                                const float *O1 = nullptr,
+                                const uint8_t *M1 = nullptr);
 size_t two_stage_ws_bytes(int32_t H, int32_t W);
 hipError_t launch_two_stage(const float *D, const uint8_t *B, const uint8_t *rgb,
                             int32_t H, int32_t W, const FilterParams &f1,

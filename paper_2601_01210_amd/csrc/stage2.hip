@@ -133,13 +133,18 @@ __device__ __forceinline__ void dense_exact(const uint4 *tile, int row0, int lx,
 // both pixels, so the tile reads per pixel drop from (2R+1)^2 to
 // (2R+2)(2R+1)/2; each pixel still takes its taps row by row, left to
 // right. T = 16 with RPT = 2 on large images, T = 8 with RPT = 1 on images
-// too small to give every CU several workgroups.
-template <int R, int T, int RPT>
+// too small to give every CU several workgroups. With RESTORE the kernel
+// stages the restored input of the two-stage filter's second pass itself:
+// a pixel's own depth where it holds a sample, else the first pass's output
+// O1 of its cell (x/3, y/3) where that is valid (M1), the values
+// k_restore_merge would have stored.
+template <int R, int T, int RPT, bool RESTORE>
 __global__ __launch_bounds__(T * T) void k_jbf_dense(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
     int tiles_x, int n_tiles, int n_pad, float *__restrict__ out,
-    uint8_t *__restrict__ mask) {
+    uint8_t *__restrict__ mask, const float *__restrict__ O1,
+    const uint8_t *__restrict__ M1) {
     static_assert(RPT == 1 || RPT == 2, "one or two rows per thread");
     constexpr int EX = T + 2 * R;             // tile width with halo
     constexpr int EY = RPT * T + 2 * R;       // tile height with halo
@@ -155,8 +160,8 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
     // clamped address and are issued before any is used; elements past the
     // tile store into one spare record.
     constexpr int NIT = (NE + NT - 1) / NT;
-    uint8_t cr[NIT][3], cv[NIT];
-    float cd[NIT];
+    uint8_t cr[NIT][3], cv[NIT], cm[NIT];
+    float cd[NIT], co[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int e = min((int)threadIdx.x + NT * it, NE - 1);
@@ -169,6 +174,11 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
         cr[it][2] = rgb[3 * p + 2];
         cv[it] = B[p];
         cd[it] = D[p];
+        if (RESTORE) {
+            const int64_t q = (int64_t)(y / 3) * ((W + 2) / 3) + x / 3;
+            cm[it] = M1[q];
+            co[it] = O1[q];
+        }
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -180,10 +190,13 @@ __global__ __launch_bounds__(T * T) void k_jbf_dense(
         float nq2h;
         colour_fields((uint32_t)cr[it][0] | ((uint32_t)cr[it][1] << 8), cr[it][2],
                       rg, b0, nq2h);
-        const bool v = in && cv[it] != 0;
+        const bool own = cv[it] != 0;
+        const bool up = RESTORE && cm[it] != 0;
+        const bool v = in && (own || up);
+        const float dv = own ? cd[it] : (up ? co[it] : 0.0f);
         // valid flag = f16 1.0 in the upper half of the (b, 0) word
         const uint4 rec = in ? make_uint4(rg, b0 | (v ? 0x3C000000u : 0u),
-                                          __float_as_uint(v ? cd[it] : 0.0f),
+                                          __float_as_uint(v ? dv : 0.0f),
                                           __float_as_uint(nq2h))
                              : make_uint4(0u, 0u, 0u, 0u);
         tile[e < NE ? e : NE] = rec;
@@ -271,25 +284,30 @@ hipError_t launch_restore_merge(const float *D, const uint8_t *B,
 hipError_t launch_densify_dense(const float *D, const uint8_t *B,
                                 const uint8_t *rgb, int32_t H, int32_t W,
                                 const FilterParams &fp, float *out,
-                                uint8_t *mask, hipStream_t s) {
+                                uint8_t *mask, hipStream_t s, const float *O1,
+                                const uint8_t *M1) {
     // 16x32 tiles (two rows per thread) when there are at least eight per
     // CU, else 8x8 tiles (one row per thread)
     const bool big = (int64_t)((W + 15) / 16) * ((H + 31) / 32) >= 2048;
+    const bool restore = O1 != nullptr;
     const int T = big ? 16 : 8, TY = big ? 32 : 8;
     const int tiles_x = (W + T - 1) / T;
     const int tiles_y = (H + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
     const int n_pad = (n_tiles + 7) & ~7;
+#define JBFD_DENSE_LAUNCH(RR, TT, RP, RS, NTH)                                  \
+    k_jbf_dense<RR, TT, RP, RS><<<n_pad, NTH, 0, s>>>(                         \
+        D, B, rgb, H, W, fp, tiles_x, n_tiles, n_pad, out, mask, O1, M1)
 #define JBFD_DENSE_CASE(RR)                                                    \
     case RR:                                                                   \
-        if (big)                                                               \
-            k_jbf_dense<RR, 16, 2><<<n_pad, 256, 0, s>>>(D, B, rgb, H, W, fp,  \
-                                                        tiles_x, n_tiles,      \
-                                                        n_pad, out, mask);     \
+        if (big && restore)                                                    \
+            JBFD_DENSE_LAUNCH(RR, 16, 2, true, 256);                           \
+        else if (big)                                                          \
+            JBFD_DENSE_LAUNCH(RR, 16, 2, false, 256);                          \
+        else if (restore)                                                      \
+            JBFD_DENSE_LAUNCH(RR, 8, 1, true, 64);                             \
         else                                                                   \
-            k_jbf_dense<RR, 8, 1><<<n_pad, 64, 0, s>>>(D, B, rgb, H, W, fp,    \
-                                                      tiles_x, n_tiles, n_pad, \
-                                                      out, mask);              \
+            JBFD_DENSE_LAUNCH(RR, 8, 1, false, 64);                            \
         break;
     switch (fp.radius) {
         JBFD_DENSE_CASE(0) JBFD_DENSE_CASE(1) JBFD_DENSE_CASE(2)
@@ -298,6 +316,7 @@ hipError_t launch_densify_dense(const float *D, const uint8_t *B,
         return hipErrorInvalidValue;
     }
 #undef JBFD_DENSE_CASE
+#undef JBFD_DENSE_LAUNCH
     return hipGetLastError();
 }
 
@@ -348,16 +367,19 @@ hipError_t launch_two_stage(const float *D, const uint8_t *B, const uint8_t *rgb
     hipError_t e = launch_pool3(D, B, rgb, H, W, D1, B1, C1, s);
     if (e != hipSuccess) return e;
     e = f1.radius <= kDenseMaxRadius
-            ? launch_densify_dense(D1, B1, C1, H1, W1, f1, O1, M1, s)
+            ? launch_densify_dense(D1, B1, C1, H1, W1, f1, O1, M1, s, nullptr,
+                                   nullptr)
             : launch_densify(D1, B1, C1, H1, W1, f1, JBFD_FP32, O1, M1, nullptr,
                              nullptr, 0, false, s);
     if (e != hipSuccess) return e;
+    // the dense kernel restores its input while staging its tiles; the
+    // sparse kernel reads a restored image
+    if (f2.radius <= kDenseMaxRadius)
+        return launch_densify_dense(D, B, rgb, H, W, f2, out, mask, s, O1, M1);
     e = launch_restore_merge(D, B, O1, M1, H, W, D2, B2, s);
     if (e != hipSuccess) return e;
-    return f2.radius <= kDenseMaxRadius
-               ? launch_densify_dense(D2, B2, rgb, H, W, f2, out, mask, s)
-               : launch_densify(D2, B2, rgb, H, W, f2, JBFD_FP32, out, mask,
-                                nullptr, nullptr, 0, false, s);
+    return launch_densify(D2, B2, rgb, H, W, f2, JBFD_FP32, out, mask, nullptr,
+                          nullptr, 0, false, s);
 }
 
 }  // namespace jbfd

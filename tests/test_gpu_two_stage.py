@@ -143,7 +143,10 @@ def test_two_stage_small_and_ragged(tdev):
     from paper_2601_01210_amd import densify_two_stage
     for (h, w, p) in [(100, 131, (4, 2.0, 15.0, 2, 2.0, 15.0)),
                       (29, 31, (6, 2.0, 12.0, 1, 1.0, 12.0)),
-                      (5, 4, (1, 1.0, 10.0, 0, 1.0, 10.0))]:
+                      (5, 4, (1, 1.0, 10.0, 0, 1.0, 10.0)),
+                      # second radius above the dense kernel's limit: the
+                      # restored image is stored and the sparse kernel reads it
+                      (61, 70, (3, 2.0, 15.0, 6, 2.0, 15.0))]:
         d, b, rgb = S.tiny_random(np.random.default_rng(h), h, w, 0.05, n_colors=5)
         ref, rmask = oracle.densify_two_stage(d, b, rgb, *p)
         out, mask = densify_two_stage(_dev(torch, dev, d), _dev(torch, dev, b),
@@ -154,3 +157,29 @@ def test_two_stage_small_and_ragged(tdev):
         sel = mask == 1
         if sel.any():
             assert (np.abs(out[sel] - ref[sel]) / np.abs(ref[sel])).max() <= 1e-5
+
+
+@pytest.mark.parametrize("h,w,r2", [(1090, 1030, 2), (100, 131, 3), (61, 70, 6)],
+                         ids=["1090x1030r2", "100x131r3", "61x70r6"])
+def test_two_stage_equals_its_steps(tdev, h, w, r2):
+    """The two-stage call (whose dense second pass restores its input while
+    staging tiles) gives bit for bit what the separate steps give: pooling,
+    first pass, the stored restore, second pass."""
+    torch, dev = tdev
+    from paper_2601_01210_amd import densify, densify_two_stage, pool3, restore_merge
+    d, b, rgb = S.tiny_random(np.random.default_rng(h * w), h, w, 0.06, n_colors=6)
+    td, tb, tc = _dev(torch, dev, d), _dev(torch, dev, b), _dev(torch, dev, rgb)
+    p = (4, 2.0, 15.0, r2, 2.0, 15.0)
+    out, mask = densify_two_stage(td, tb, tc, *p)
+    d1, b1, c1 = pool3(td, tb, tc)
+    o1, m1 = densify(d1, b1, c1, p[0], p[1], p[2], dense=True)
+    d2, b2 = restore_merge(td, tb, o1, m1)
+    if r2 <= 4:
+        o2, m2 = densify(d2, b2, tc, r2, p[4], p[5], dense=True)
+    else:
+        o2, m2 = densify(d2, b2, tc, r2, p[4], p[5], ws=None)
+    torch.cuda.synchronize()
+    print(f"two-stage steps {h}x{w} r2={r2}: valid {float(mask.float().mean()):.3f}",
+          flush=True)
+    assert torch.equal(mask, m2)
+    assert torch.equal(out.view(torch.int32), o2.view(torch.int32))
