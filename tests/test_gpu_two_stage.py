@@ -33,7 +33,10 @@ def _dev(torch, dev, a):
 
 
 @pytest.mark.parametrize("h,w,dens", [(7, 8, 0.3), (90, 121, 0.07),
-                                      (360, 640, 0.5), (1, 1, 1.0), (2, 5, 0.0)])
+                                      (360, 640, 0.5), (1, 1, 1.0), (2, 5, 0.0),
+                                      # 534 cells a row: three workgroups,
+                                      # the last one partly outside
+                                      (31, 1600, 0.3)])
 def test_pool3_bit_exact(tdev, h, w, dens):
     torch, dev = tdev
     from paper_2601_01210_amd import pool3
