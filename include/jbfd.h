@@ -182,17 +182,23 @@ jbfd_status jbfd_project_recycled(const float *pts_xyz, int64_t n,
                                   void *stream);
 
 /*
- * jbfd_project_recycled followed by jbfd_densify with sample lists, in one
- * call that fuses the decode of the key image with the counting pass of the
- * list build (the decode reads each unit's halo keys itself, and the list
- * scatter clears the keys once the lists are written). Results are those of
- * the two calls made separately, bit for bit: sparse_depth / sparse_valid
- * as jbfd_project_recycled (required), dense_depth / dense_valid as
- * jbfd_densify with the same workspace (no aux). zbuf holds only empty keys
- * on entry and is left so (as for jbfd_project_recycled). When ws cannot
- * hold the lists' tables (see jbfd_densify_ws_bytes), the call projects with
- * jbfd_project_recycled and the filter streams its inputs. Errors as
- * jbfd_project and jbfd_densify; sizes come from K.
+ * The whole path of one viewpoint (Sec. 2: projection of the merged sweeps
+ * into the camera with a nearest-depth z-buffer; Sec. 4.2, Eq. 1-4 and
+ * Algorithm 1: the joint bilateral filter): jbfd_project_recycled followed
+ * by jbfd_densify with sample lists, in one call that fuses the decode of
+ * the key image with the counting pass of the list build (the decode reads
+ * each unit's halo keys itself, and the list scatter clears the keys once
+ * the lists are written). Results are those of the two calls made
+ * separately, bit for bit: sparse_depth / sparse_valid as
+ * jbfd_project_recycled (required, device, W*H), dense_depth / dense_valid
+ * as jbfd_densify with the same workspace (required, device, W*H; no aux).
+ * zbuf holds only empty keys on entry and is left so (as for
+ * jbfd_project_recycled). ws, ws_bytes: NULL/0, or a device workspace,
+ * 256-byte aligned (else JBFD_EINVAL), as for jbfd_densify; when ws is NULL
+ * or cannot hold the lists' tables (see jbfd_densify_ws_bytes), the call
+ * projects with jbfd_project_recycled and the filter streams its inputs.
+ * Other errors as jbfd_project and jbfd_densify; sizes come from K. The
+ * caller owns every buffer; calls that share zbuf or ws must be ordered.
  */
 jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
                                  const double cam_from_world[12],
