@@ -204,6 +204,61 @@ def test_project_densify_equals_separate_calls(torch_dev, case):
             assert np.all(zb.cpu().numpy().view(np.uint64) == empty)
 
 
+def test_project_densify_graph_replays(torch_dev):
+    """jbfd_project_densify captured in a HIP graph: every replay, with eager
+    work of the same kind and synchronisations between the replays, gives
+    the eager call's results bit for bit and leaves the key buffer empty
+    (the key buffer is cleared by kernel stores, so replays need no memset
+    node)."""
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import densify_workspace, project_densify, zbuf_clear
+    w, h, r = 640, 360, 15
+    rng = np.random.default_rng(77)
+    pose = np.hstack([np.eye(3), np.zeros((3, 1))])
+    intr = (0.7 * w, 0.7 * w, w / 2.0, h / 2.0)
+    rgb = torch.from_numpy(rng.integers(0, 256, size=(h, w, 3), dtype=np.uint8)).to(dev)
+    pts = rng.normal(0, 1.0, size=(20000, 3)).astype(np.float32)
+    pts[:, 2] = np.abs(pts[:, 2]) * 4 + 0.5
+    p = torch.from_numpy(pts).to(dev)
+    other = torch.from_numpy(pts[::-1].copy() * np.float32(1.1)).to(dev)
+    ws = densify_workspace(h, w, r, 20000, device=dev)
+    ws_e = torch.empty_like(ws)
+    ze = zbuf_clear(torch.empty((h, w), dtype=torch.int64, device=dev))
+    ref = [t.clone() for t in project_densify(p, pose, intr, w, h, rgb, r, 3.0, 12.0,
+                                              ze, ws_e)]
+    zg = zbuf_clear(torch.empty((h, w), dtype=torch.int64, device=dev))
+    outs = (torch.empty((h, w), dtype=torch.float32, device=dev),
+            torch.empty((h, w), dtype=torch.uint8, device=dev),
+            torch.empty((h, w), dtype=torch.float32, device=dev),
+            torch.empty((h, w), dtype=torch.uint8, device=dev))
+
+    def call():
+        return project_densify(p, pose, intr, w, h, rgb, r, 3.0, 12.0, zg, ws,
+                               depth=outs[0], valid=outs[1], out=outs[2], mask=outs[3])
+
+    call()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+        call()
+    torch.cuda.synchronize()
+    empty = np.uint64(2 ** 64 - 1)
+    for rep in range(4):
+        print(f"graph replay {rep}", flush=True)
+        for t in outs:
+            t.fill_(7)
+        # eager work between replays: another frame through the same kernels
+        project_densify(other, pose, intr, w, h, rgb, r, 3.0, 12.0, ze, ws_e)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), rep
+        assert np.all(zg.cpu().numpy().view(np.uint64) == empty)
+
+
 def test_project_largest_sides(torch_dev):
     """Images of the largest side (32767) in either direction, with points
     spread over the whole width or height: keys bit-exact."""
