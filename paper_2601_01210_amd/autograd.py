@@ -19,6 +19,7 @@ from __future__ import annotations
 import dataclasses
 import json
 import math
+import os
 from typing import List, Optional, Sequence
 
 from . import binding
@@ -99,18 +100,40 @@ class FitFrame:
 def fit_sigmas(frames: Sequence[FitFrame], radius: int, sigma_s0: float,
                sigma_r0: float, steps: int = 200, lr: float = 0.05,
                betas=(0.9, 0.999), eps: float = 1e-8,
-               log: Optional[list] = None):
+               log: Optional[list] = None, checkpoint: Optional[str] = None,
+               resume: bool = False):
     """Adam on (sigma_s, sigma_r) minimising the held-out L1 loss summed over
-    the frames' contributing targets. Returns (sigma_s, sigma_r, history)."""
+    the frames' contributing targets. Returns (sigma_s, sigma_r, history).
+
+    ``checkpoint``: a JSON file rewritten (atomically) after every step with
+    the widths, Adam's moments and step count, and the history; with
+    ``resume`` the fit continues from that file when it exists, so an
+    interrupted fit of ``steps`` steps ends where an uninterrupted one would.
+    """
     torch = _torch()
     dev = frames[0].depth.device
     params = torch.tensor([sigma_s0, sigma_r0], dtype=torch.float64,
                           device=dev, requires_grad=True)
     opt = torch.optim.Adam([params], lr=lr, betas=betas, eps=eps)
-    history = []
-    for step in range(steps):
+    history: List[dict] = []
+    start = 0
+    if resume and checkpoint and os.path.exists(checkpoint):
+        st = load_state(checkpoint)
+        with torch.no_grad():
+            params.copy_(torch.tensor([st["sigma_s"], st["sigma_r"]],
+                                      dtype=torch.float64))
+        adam = st["adam"]
+        if adam["step"] > 0:
+            opt.state[params] = {
+                "step": torch.tensor(float(adam["step"])),
+                "exp_avg": torch.tensor(adam["exp_avg"], dtype=torch.float64,
+                                        device=dev),
+                "exp_avg_sq": torch.tensor(adam["exp_avg_sq"],
+                                           dtype=torch.float64, device=dev)}
+        history = list(st["history"])
+        start = int(st["step"])
+    for step in range(start, steps):
         opt.zero_grad()
-        total = 0.0
         count = 0
         losses = []
         for f in frames:
@@ -125,16 +148,36 @@ def fit_sigmas(frames: Sequence[FitFrame], radius: int, sigma_s0: float,
         opt.step()
         with torch.no_grad():
             params.clamp_(min=MIN_SIGMA)
-        rec = {"step": step, "loss": float(loss), "sigma_s": float(params[0]),
-               "sigma_r": float(params[1]), "targets": count}
+        p = params.detach().cpu().tolist()
+        rec = {"step": step, "loss": float(loss.detach()), "sigma_s": p[0],
+               "sigma_r": p[1], "targets": count}
         history.append(rec)
         if log is not None:
             log.append(rec)
+        if checkpoint:
+            save_state(checkpoint, p[0], p[1], history, opt.state[params],
+                       step + 1)
     return float(params[0]), float(params[1]), history
 
 
-def save_state(path: str, sigma_s: float, sigma_r: float, history) -> None:
-    """Checkpoint of the fit (the only state worth saving)."""
-    with open(path, "w") as f:
-        json.dump({"sigma_s": sigma_s, "sigma_r": sigma_r,
-                   "history": history}, f)
+def save_state(path: str, sigma_s: float, sigma_r: float, history,
+               adam_state=None, step: Optional[int] = None) -> None:
+    """Checkpoint of the fit: the widths, Adam's moments and step count, and
+    the history, written to a temporary file and renamed over ``path``."""
+    adam = {"step": 0, "exp_avg": [0.0, 0.0], "exp_avg_sq": [0.0, 0.0]}
+    if adam_state:
+        adam = {"step": int(float(adam_state["step"])),
+                "exp_avg": adam_state["exp_avg"].detach().cpu().tolist(),
+                "exp_avg_sq": adam_state["exp_avg_sq"].detach().cpu().tolist()}
+    state = {"sigma_s": sigma_s, "sigma_r": sigma_r,
+             "step": len(history) if step is None else step, "adam": adam,
+             "history": history}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(state, f)
+    os.replace(tmp, path)
+
+
+def load_state(path: str) -> dict:
+    with open(path) as f:
+        return json.load(f)
