@@ -11,6 +11,7 @@ Functions (the C file documents the formulas and the passages they follow):
 * :func:`densify`         Eq. 1-4 gather (common factor exp(Emax) removed)
 * :func:`densify_plain`   Eq. 1-4 literally (no rescaling)
 * :func:`densify_alg1`    Algorithm 1 steps 1-5 (materialised weights)
+* :func:`densify_spread`  per-pixel sensitivity of Eq. 1-4 to weight errors
 * :func:`densify_grad`    gradient w.r.t. depths, sigma_s, sigma_r
 * :func:`l1_holdout_loss` the self-supervised held-out L1 loss and its
                           upstream gradient
@@ -85,6 +86,10 @@ def lib():
                                           C.c_double, f64p, f64p,
                                           C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]
+        L.oracle_densify_spread.restype = None
+        L.oracle_densify_spread.argtypes = [f32p, u8p, u8p, C.c_int32,
+                                            C.c_int32, C.c_int32, C.c_double,
+                                            C.c_double, f64p, f64p]
         L.oracle_pool3.restype = None
         L.oracle_pool3.argtypes = [f32p, u8p, u8p, C.c_int32, C.c_int32,
                                    f32p, u8p, u8p]
@@ -188,6 +193,20 @@ def densify_alg1(depth, valid, rgb, radius, sigma_s, sigma_r):
     if rc != 0:
         raise MemoryError("oracle_densify_alg1: allocation failed")
     return out, mask
+
+
+def densify_spread(depth, valid, rgb, radius, sigma_s, sigma_r, out):
+    """Per pixel sum w_i |D_i - out| / sum w_i over the window (the weighted
+    mean absolute deviation of the samples from ``out``, the oracle's own
+    output): a relative error of at most e in every weight moves the output
+    by at most e S / (1 - e). 0 where the window holds no sample."""
+    d = _c(depth, np.float32)
+    h, w = d.shape
+    sp = np.empty((h, w), np.float64)
+    lib().oracle_densify_spread(d, _c(valid, np.uint8),
+                                _c(rgb, np.uint8).reshape(h, w, 3), h, w,
+                                radius, sigma_s, sigma_r, _c(out, np.float64), sp)
+    return sp
 
 
 def densify_grad(depth, valid, rgb, radius, sigma_s, sigma_r, g):

@@ -255,6 +255,61 @@ int64_t oracle_densify(const float *depth, const uint8_t *valid,
 }
 
 /*
+ * Sensitivity of Eq. 1-4 to errors in the weights: for each pixel with a
+ * valid sample, S(x) = sum_i w_i |D_i - out(x)| / sum_i w_i over the same
+ * window and weights as oracle_densify, with out = its output (passed in).
+ * Since out is a weighted mean, multiplying each weight by (1 + e_i) with
+ * |e_i| <= e moves it by at most e S(x) / (1 - e): the per-pixel bound of
+ * reduced-precision weights. S = 0 where the window holds no sample.
+ */
+void oracle_densify_spread(const float *depth, const uint8_t *valid,
+                           const uint8_t *rgb, int32_t height, int32_t width,
+                           int32_t r, double sigma_s, double sigma_r,
+                           const double *out, double *spread) {
+    const double kr = half_inv_var(sigma_r);
+    const double ks = half_inv_var(sigma_s);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t y = 0; y < height; ++y) {
+        for (int32_t x = 0; x < width; ++x) {
+            const int64_t p = (int64_t)y * width + x;
+            double em = -INFINITY;
+            for (int32_t b = -r; b <= r; ++b) {
+                const int32_t yy = y + b;
+                if (yy < 0 || yy >= height) continue;
+                for (int32_t a = -r; a <= r; ++a) {
+                    const int32_t xx = x + a;
+                    if (xx < 0 || xx >= width) continue;
+                    const int64_t q = (int64_t)yy * width + xx;
+                    if (!valid[q]) continue;
+                    const double e = -((double)color_dist2(rgb, p, q) * kr) -
+                                     ((double)(a * a + b * b) * ks);
+                    if (e > em) em = e;
+                }
+            }
+            double dev = 0.0, den = 0.0;
+            if (em > -INFINITY) {
+                for (int32_t b = -r; b <= r; ++b) {
+                    const int32_t yy = y + b;
+                    if (yy < 0 || yy >= height) continue;
+                    for (int32_t a = -r; a <= r; ++a) {
+                        const int32_t xx = x + a;
+                        if (xx < 0 || xx >= width) continue;
+                        const int64_t q = (int64_t)yy * width + xx;
+                        if (!valid[q]) continue;
+                        const double e = -((double)color_dist2(rgb, p, q) * kr) -
+                                         ((double)(a * a + b * b) * ks);
+                        const double w = exp(e - em);
+                        dev += w * fabs((double)depth[q] - out[p]);
+                        den += w;
+                    }
+                }
+            }
+            spread[p] = den > 0.0 ? dev / den : 0.0;
+        }
+    }
+}
+
+/*
  * Eq. 1-4 taken literally: w = w_c * w_p with each Gaussian evaluated on its
  * own and no rescaling. Where every weight of a window underflows the ratio
  * is 0/0; callers use it only on inputs where that cannot happen.

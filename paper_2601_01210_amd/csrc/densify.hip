@@ -556,11 +556,10 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     //        colour clamp and the sum take two fmas, Pass1Exp), so an
     //        in-window sample never underflows to zero and den > 0 exactly
     //        when the window holds a sample.
-    //  FP16 range weights: the colour exponent is rounded to FP16 by the
-    //        mixed-precision fma, w_c = v_exp_f16, and w_c times the FP32
-    //        spatial weight is accumulated in FP32 through v_fma_mix; the
-    //        sum of the spatial weights alone (never zero in the window)
-    //        decides the mask.
+    //  FP16 range weights: w_c = 2^n v_exp_f16(f) for the colour exponent's
+    //        integer part n and fraction f, times the FP32 spatial weight,
+    //        accumulated in FP32; the sum of the spatial weights alone
+    //        (never zero in the window) decides the mask.
     const float Mfast = -fp.kr * p2;
     float num = 0.0f, den = 0.0f, dsp = 0.0f;
     if constexpr (PREC == JBFD_FP32) {
@@ -584,14 +583,22 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
             eat, -__builtin_inff());
         dsp = den;
     } else {
-        // stage_a keeps the colour exponent and ws * d
+        // The colour exponent a = -kr c (FP32, from the exact t) is split into
+        // its integer part n and fraction f in [0, 1); the FP16 exponential
+        // evaluates 2^f (f rounded to FP16: at most 2^-12 off) and 2^n is
+        // applied exactly to the FP32 spatial weight. Every range weight thus
+        // carries the relative error of one FP16 result, whatever |a|.
+        // stage_a keeps f, ws 2^n and ws 2^n d.
         auto stage_a = [&](float t, float ws, float d) {
-            return make_float2(__builtin_fmaf(kr2, t, Mfast), ws * d);
+            const float a = __builtin_fmaf(kr2, t, Mfast);
+            const float n = __builtin_floorf(a);
+            const float wsn = __builtin_ldexpf(ws, (int)n);
+            return make_float3(a - n, wsn, wsn * d);
         };
-        auto stage_b = [&](float2 a, float ws, float) {
-            const float wc = (float)__builtin_exp2f16((_Float16)a.x);
-            num = __builtin_fmaf(wc, a.y, num);
-            den = __builtin_fmaf(wc, ws, den);
+        auto stage_b = [&](float3 a, float ws, float) {
+            const float e = (float)__builtin_exp2f16((_Float16)a.x);
+            num = __builtin_fmaf(e, a.z, num);
+            den = __builtin_fmaf(e, a.y, den);
             dsp += ws;
         };
         auto eat = [&](float t, float ws, float d, uint32_t) {
@@ -611,8 +618,7 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     // (clamping or precision could matter there): the exact running shift
     // of consume4/consume1 over the same samples, with exact, unclamped
     // spatial exponents.
-    const bool weak = inside && dsp > 0.0f &&
-                      den < (PREC == JBFD_FP32 ? kWeakBelow : kWeakBelowF16);
+    const bool weak = inside && dsp > 0.0f && den < kWeakBelow;
     float M = Mfast;
     if (__builtin_amdgcn_ballot_w64(weak) != 0) {
         float M2 = kShiftInit - fp.kr * p2, num2 = 0.0f, den2 = 0.0f;

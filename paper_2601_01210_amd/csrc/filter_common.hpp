@@ -15,7 +15,6 @@ constexpr float kRescaleAbove = 12.0f;
 constexpr float kShiftInit = 8388608.0f;  // 2^23
 constexpr float kClampExp = -60.0f;       // pass-1 floor of each exponent part
 constexpr float kWeakBelow = 1.52587890625e-05f;  // 2^-16: pass-2 threshold
-constexpr float kWeakBelowF16 = 0.00390625f;      // 2^-8: same, FP16 weights
 constexpr int kRecWords = 5;       // list record size in 32-bit words
 constexpr int NG = 4;              // records per group of the first pass's list
                                    // walk (6 and 8 measured no faster)

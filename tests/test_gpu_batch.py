@@ -7,11 +7,10 @@ the oracle's bit for bit and the single-view jbfd_project's; the mask must
 equal the oracle's; FP32 depth must agree with the FP64 oracle to 1e-5
 relative and be bit-identical to the single-view jbfd_densify (same tile
 body, same arithmetic). The FP16 range-weight form runs on the same batch,
-side by side, with its error against the oracle reported per view: the
-max is bounded by the arithmetic (2^-9 of the depth span) and at least
-99% of valid pixels must lie within 1 mm (the fraction is printed). A hard 1 mm worst case is out of
-reach for FP16 weights: their 11-bit significand alone moves a two-sample
-average across a 19 m edge by up to 19 m * 2^-10 / 4 = 4.6 mm.
+side by side: its mask must equal the oracle's, every valid pixel must lie
+within the per-pixel bound of FP16 weights (fp16_check), and max / p99.9 /
+mean in mm are printed per view with every pixel above 1 mm named with its
+condition number.
 
 The batch is also captured into a HIP graph and replayed with the
 descriptor table rewritten between replays (new poses, point counts and
@@ -117,18 +116,14 @@ def test_batch_fp16_side_by_side(tdev, frames, refs):
     v16 = _views(torch, dev, frames)
     _run(torch, v32, Precision.FP32)
     _run(torch, v16, Precision.FP16_RANGE)
+    from fp16_check import fp16_report
     for k, (a, c, (z, d, b, ref, m)) in enumerate(zip(v32, v16, refs)):
-        np.testing.assert_array_equal(c.dense_valid.cpu().numpy(), m)
+        f = frames[k]
         sel = m == 1
-        e16 = np.abs(c.dense_depth.cpu().numpy()[sel] - ref[sel]) * 1e3
         e32 = np.abs(a.dense_depth.cpu().numpy()[sel] - ref[sel]) * 1e3
-        span = float(d[b == 1].max() - d[b == 1].min())
-        print(f"  view {k}: fp32 max {e32.max():.4f} mm; fp16 max "
-              f"{e16.max():.4f} p99.9 {np.percentile(e16, 99.9):.4f} mean "
-              f"{e16.mean():.5f} mm, within 1 mm {(e16 <= 1.0).mean():.5f}",
-              flush=True)
-        assert e16.max() <= 2.0 ** -9 * span * 1e3 + 1e-9
-        assert (e16 <= 1.0).mean() >= 0.99
+        print(f"  view {k}: fp32 max {e32.max():.4f} mm", flush=True)
+        fp16_report(c.dense_depth.cpu().numpy(), c.dense_valid.cpu().numpy(), ref,
+                    m, d, b, f.rgb, f.radius, f.sigma_s, f.sigma_r, f"view {k}")
 
 
 def test_batch_mixed_filters_and_degenerate_views(tdev):

@@ -1,19 +1,14 @@
 """GPU checks of the FP16 range-weight form and of the backward pass.
 
 FP16 range weights: the mask is structural and must match the FP64 oracle
-bit for bit; the depth error against the oracle is reported per result in
-millimetres (max, p99.9, mean) and bounded. The bound follows from the
-arithmetic: each range weight carries the FP16 rounding of its exponent,
-ln(2) |e| 2^-11 relative (|e| <= 24 before the weight underflows), plus
-2^-11 from v_exp_f16; the depth error is at most that relative weight error
-times max |D_i - out| over the window (at most 19 m for 1-20 m scenes).
-Pixels whose weights would sit in the FP16 subnormal range are recomputed
-exactly in FP32, so the per-weight error stays near 2^-11..2^-9. The tests
-assert max error <= 2^-9 of the depth span everywhere and at least 99%
-of valid pixels within 1 mm on the synthetic scenes (a hard 1 mm worst case
-is out of reach: the 11-bit significand of an FP16 weight alone moves a
-two-sample average across a 19 m edge by up to 19 m * 2^-10 / 4 = 4.6 mm); the random case (every window mixes 1..20 m depths of
-unrelated colours) is the adversarial one and is only bounded by the span.
+bit for bit; every valid pixel's depth must lie within the per-pixel bound
+of FP16 weights (fp16_check: one FP16 result per weight, so the error is
+at most about 2^-10 times the window's weighted mean absolute deviation from
+the output), p99.9 of the error must stay within 1 mm on the two
+single-view configurations, and max / p99.9 / mean are printed per result
+with every pixel above 1 mm named with its condition number. The random
+case (every window mixes 1..20 m depths of unrelated colours) is the
+adversarial one and is held to the per-pixel bound only.
 
 Backward: GPU gradients vs the FP64 oracle's analytic gradient (dense and
 held-out-sparse upstream gradients), vs central finite differences of the
@@ -41,22 +36,10 @@ def _dev(torch, dev, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def fp16_stats(out, mask, ref, rmask):
-    np.testing.assert_array_equal(mask, rmask)
-    sel = mask == 1
-    err = np.abs(out[sel].astype(np.float64) - ref[sel])
-    mm = err * 1e3
-    return {"max_mm": float(mm.max()) if mm.size else 0.0,
-            "p999_mm": float(np.percentile(mm, 99.9)) if mm.size else 0.0,
-            "mean_mm": float(mm.mean()) if mm.size else 0.0,
-            "max_rel": float((err / ref[sel]).max()) if mm.size else 0.0,
-            "within_1mm": float((mm <= 1.0).mean()) if mm.size else 1.0,
-            "n": int(sel.sum())}
-
-
 @pytest.mark.parametrize("cfg", ["small", "fullhd", "random"])
 def test_fp16_range_against_oracle(tdev, cfg):
     torch, dev = tdev
+    from fp16_check import fp16_report
     from paper_2601_01210_amd import Precision, densify
     if cfg == "random":
         d, b, rgb = S.tiny_random(np.random.default_rng(2), 97, 131, 0.08,
@@ -76,12 +59,9 @@ def test_fp16_range_against_oracle(tdev, cfg):
                             precision=Precision.FP16_RANGE, ws=ws,
                             max_samples=int(b.sum()))
         torch.cuda.synchronize()
-        st = fp16_stats(out.cpu().numpy(), mask.cpu().numpy(), ref, rmask)
-        print(f"  fp16-range {cfg} ws={ws}: {st}", flush=True)
-        span = float(d[b == 1].max() - d[b == 1].min()) if b.any() else 0.0
-        assert st["max_mm"] <= 2.0 ** -9 * span * 1e3 + 1e-9
-        if cfg != "random":
-            assert st["within_1mm"] >= 0.99
+        fp16_report(out.cpu().numpy(), mask.cpu().numpy(), ref, rmask, d, b, rgb,
+                    r, ss, sr, f"{cfg} ws={ws}",
+                    p999_mm=None if cfg == "random" else 1.0)
 
 
 def _gpu_grad(torch, dev, d, b, rgb, r, ss, sr, g):
@@ -201,7 +181,8 @@ def test_autograd_and_short_fit(tdev):
                                      cam.width, cam.height)
         frames.append(AG.FitFrame(dd, vv, torch.from_numpy(f.rgb).to(dev),
                                   tdp, tv))
-    # gradient through autograd equals the binding's backward
+    # one autograd step through the hand-written backward (its value is
+    # checked against the oracle and the binding in test_gpu_fit_chain)
     ss = torch.tensor(2.0, dtype=torch.float64, device=dev, requires_grad=True)
     sr = torch.tensor(40.0, dtype=torch.float64, device=dev, requires_grad=True)
     fr = frames[0]
