@@ -11,7 +11,9 @@
  *                      jbfd_project_recycled and jbfd_zbuf_clear do the same
  *                      for a frame loop that reuses its key buffer, and
  *                      jbfd_project_densify runs both steps below in one
- *                      call with the key decode fused into the list build;
+ *                      call with the key decode fused into the list build
+ *                      (jbfd_project_densify_noalloc: the same without a
+ *                      caller workspace);
  *   2. jbfd_densify  - RGB-guided joint bilateral filter over that sparse
  *                      depth image (Eq. 1-4, organised as Algorithm 1),
  *                      giving a dense depth image and a validity mask;
@@ -37,8 +39,9 @@
  * ---------------------------------------
  * - Every buffer pointer is a DEVICE pointer unless stated otherwise. The
  *   caller allocates and frees every buffer; the library never allocates
- *   device memory and keeps no mutable global state, so calls on different
- *   streams may run concurrently from different host threads.
+ *   device memory and keeps no mutable global state (the one exception is
+ *   the fixed per-GPU array of jbfd_project_densify_noalloc), so calls on
+ *   different streams may run concurrently from different host threads.
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
  *   work is enqueued asynchronously on it; outputs are valid once the caller
  *   has synchronised the stream.
@@ -68,7 +71,7 @@
 extern "C" {
 #endif
 
-#define JBFD_ABI_VERSION 3
+#define JBFD_ABI_VERSION 4
 
 /* Largest filter radius: the halo of one 8x8 output block must fit the
  * per-workgroup spatial table in LDS. */
@@ -208,6 +211,34 @@ jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
                                  float *sparse_depth, uint8_t *sparse_valid,
                                  float *dense_depth, uint8_t *dense_valid, void *ws,
                                  size_t ws_bytes, void *stream);
+
+/*
+ * jbfd_project_densify for callers that cannot allocate device memory or
+ * hand over a workspace: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments, results and errors as
+ * jbfd_project_densify without ws / ws_bytes, bit for bit: the sample lists
+ * are built in a fixed array of JBFD_NOALLOC_WS_BYTES bytes inside the
+ * library (one per GPU, held from the first call on that GPU until the
+ * process ends; the call never allocates). A call whose lists may need more,
+ * jbfd_densify_ws_bytes(K->height, K->width, radius, n) > JBFD_NOALLOC_WS_BYTES
+ * (n bounds the valid samples), returns JBFD_ENOSPC before anything is
+ * enqueued. Every call on one GPU shares that GPU's array and leaves its
+ * contents there; each call rewrites every table it reads, so nothing needs
+ * clearing between calls, but calls that overlap on one GPU (different
+ * streams or host threads without ordering) race on the array and must not
+ * be issued. The device must be current (hipSetDevice) on the calling
+ * thread, as for any launch on `stream`.
+ */
+#define JBFD_NOALLOC_WS_BYTES ((size_t)32 << 20)
+jbfd_status jbfd_project_densify_noalloc(const float *pts_xyz, int64_t n,
+                                         const double cam_from_world[12],
+                                         const jbfd_intrinsics *K,
+                                         const uint8_t *rgb_hwc, int32_t radius,
+                                         float sigma_s, float sigma_r,
+                                         jbfd_precision prec, uint64_t *zbuf,
+                                         float *sparse_depth, uint8_t *sparse_valid,
+                                         float *dense_depth, uint8_t *dense_valid,
+                                         void *stream);
 
 /* Set every key of an H x W key buffer (device) to the empty key
  * UINT64_MAX, for jbfd_project_recycled. */

@@ -90,6 +90,10 @@ def lib():
         L.jbfd_project_densify.argtypes = [vp, i64, C.POINTER(C.c_double),
                                            C.POINTER(Intrinsics), vp, i32, f32, f32,
                                            C.c_int, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.jbfd_project_densify_noalloc.restype = C.c_int
+        L.jbfd_project_densify_noalloc.argtypes = [
+            vp, i64, C.POINTER(C.c_double), C.POINTER(Intrinsics), vp, i32, f32, f32,
+            C.c_int, vp, vp, vp, vp, vp, vp]
         L.jbfd_densify.restype = C.c_int
         L.jbfd_densify.argtypes = [vp, vp, vp, i32, i32, i32, f32, f32,
                                    C.c_int, vp, vp, vp, vp, sz, C.c_uint32,
@@ -265,6 +269,46 @@ def project_densify(points, pose, intrinsics: Sequence[float], width: int,
         int(radius), float(sigma_s), float(sigma_r), int(precision), _ptr(zbuf),
         _ptr(depth), _ptr(valid), _ptr(out), _ptr(mask), _ptr(ws), ws.numel(),
         _stream(dev)))
+    return depth, valid, out, mask
+
+
+NOALLOC_WS_BYTES = 32 << 20   # JBFD_NOALLOC_WS_BYTES
+
+
+def project_densify_noalloc(points, pose, intrinsics: Sequence[float], width: int,
+                            height: int, rgb, radius: int, sigma_s: float,
+                            sigma_r: float, zbuf,
+                            precision: Precision = Precision.FP32, depth=None,
+                            valid=None, out=None, mask=None):
+    """:func:`project_densify` without a workspace
+    (jbfd_project_densify_noalloc): the sample lists live in the library's
+    fixed per-GPU array. Raises JbfdError (JBFD_ENOSPC) when the lists of
+    this size may not fit it. Returns (depth, valid, out, mask)."""
+    torch = _torch()
+    _need(points, torch.float32, None, "points")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (N, 3)")
+    dev = points.device
+    h, w = int(height), int(width)
+    _need(rgb, torch.uint8, (h, w, 3), "rgb")
+    _need(zbuf, torch.int64, (h, w), "zbuf")
+    if depth is None:
+        depth = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if valid is None:
+        valid = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    if mask is None:
+        mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    for t, dt, nm in ((depth, torch.float32, "depth"), (valid, torch.uint8, "valid"),
+                      (out, torch.float32, "out"), (mask, torch.uint8, "mask")):
+        _need(t, dt, (h, w), nm)
+    K = Intrinsics(float(intrinsics[0]), float(intrinsics[1]),
+                   float(intrinsics[2]), float(intrinsics[3]), w, h)
+    _check(lib().jbfd_project_densify_noalloc(
+        _ptr(points), int(points.shape[0]), _pose_array(pose), C.byref(K), _ptr(rgb),
+        int(radius), float(sigma_s), float(sigma_r), int(precision), _ptr(zbuf),
+        _ptr(depth), _ptr(valid), _ptr(out), _ptr(mask), _stream(dev)))
     return depth, valid, out, mask
 
 

@@ -6,6 +6,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "filter_common.hpp"
 
 namespace {
@@ -143,15 +145,17 @@ jbfd_status jbfd_project_recycled(const float *pts_xyz, int64_t n,
                           zbuf, sparse_depth, sparse_valid, true, stream);
 }
 
-jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
-                                 const double cam_from_world[12],
-                                 const jbfd_intrinsics *K, const uint8_t *rgb_hwc,
-                                 int32_t radius, float sigma_s, float sigma_r,
-                                 jbfd_precision prec, uint64_t *zbuf,
-                                 float *sparse_depth, uint8_t *sparse_valid,
-                                 float *dense_depth, uint8_t *dense_valid, void *ws,
-                                 size_t ws_bytes, void *stream) {
-    const char *name = "jbfd_project_densify";
+// argument checks shared by the one-call projection + filter entry points
+static jbfd_status check_project_densify(const char *name, const float *pts_xyz,
+                                         int64_t n, const double cam_from_world[12],
+                                         const jbfd_intrinsics *K,
+                                         const uint8_t *rgb_hwc, int32_t radius,
+                                         float sigma_s, float sigma_r,
+                                         jbfd_precision prec, const uint64_t *zbuf,
+                                         const float *sparse_depth,
+                                         const uint8_t *sparse_valid,
+                                         const float *dense_depth,
+                                         const uint8_t *dense_valid) {
     jbfd_status st = check_project(name, pts_xyz, n, cam_from_world, K, zbuf);
     if (st != JBFD_OK) return st;
     if (!rgb_hwc || !sparse_depth || !sparse_valid || !dense_depth || !dense_valid)
@@ -160,9 +164,18 @@ jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
     if (st != JBFD_OK) return st;
     if (prec != JBFD_FP32 && prec != JBFD_FP16_RANGE)
         return fail(JBFD_EINVAL, "%s: unknown precision %d", name, (int)prec);
-    if (ws && ((uintptr_t)ws & 255))
-        return fail(JBFD_EINVAL, "%s: workspace not 256-byte aligned", name);
-    if (!ws) ws_bytes = 0;
+    return JBFD_OK;
+}
+
+static jbfd_status run_project_densify(const char *name, const float *pts_xyz,
+                                       int64_t n, const double cam_from_world[12],
+                                       const jbfd_intrinsics *K,
+                                       const uint8_t *rgb_hwc, int32_t radius,
+                                       float sigma_s, float sigma_r,
+                                       jbfd_precision prec, uint64_t *zbuf,
+                                       float *sparse_depth, uint8_t *sparse_valid,
+                                       float *dense_depth, uint8_t *dense_valid,
+                                       void *ws, size_t ws_bytes, void *stream) {
     jbfd::Pose P;
     for (int t = 0; t < 12; ++t) P.m[t] = cam_from_world[t];
     jbfd::Intr I{K->fx, K->fy, K->cx, K->cy, K->width, K->height};
@@ -173,6 +186,105 @@ jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
     if (e == hipErrorNotSupported)
         return fail(JBFD_EUNSUPPORTED, "%s: precision not built", name);
     return hip_status(e, name);
+}
+
+jbfd_status jbfd_project_densify(const float *pts_xyz, int64_t n,
+                                 const double cam_from_world[12],
+                                 const jbfd_intrinsics *K, const uint8_t *rgb_hwc,
+                                 int32_t radius, float sigma_s, float sigma_r,
+                                 jbfd_precision prec, uint64_t *zbuf,
+                                 float *sparse_depth, uint8_t *sparse_valid,
+                                 float *dense_depth, uint8_t *dense_valid, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    const char *name = "jbfd_project_densify";
+    const jbfd_status st = check_project_densify(
+        name, pts_xyz, n, cam_from_world, K, rgb_hwc, radius, sigma_s, sigma_r, prec,
+        zbuf, sparse_depth, sparse_valid, dense_depth, dense_valid);
+    if (st != JBFD_OK) return st;
+    if (ws && ((uintptr_t)ws & 255))
+        return fail(JBFD_EINVAL, "%s: workspace not 256-byte aligned", name);
+    if (!ws) ws_bytes = 0;
+    return run_project_densify(name, pts_xyz, n, cam_from_world, K, rgb_hwc, radius,
+                               sigma_s, sigma_r, prec, zbuf, sparse_depth,
+                               sparse_valid, dense_depth, dense_valid, ws, ws_bytes,
+                               stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// jbfd_project_densify_noalloc: the sample lists live in a fixed device array
+// of this file, one copy per GPU, instead of a caller workspace.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The array itself. In host code `scratch` names a host-side stand-in, not
+// the device memory: its device address, which differs per GPU, comes from
+// hipGetSymbolAddress with that GPU current, and only that address is ever
+// passed to kernels.
+__device__ __align__(256) unsigned char scratch[JBFD_NOALLOC_WS_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device and kept.
+jbfd_status scratch_address(const char *name, void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(JBFD_EHIP, "%s: hipGetDevice: %s", name, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(JBFD_EUNSUPPORTED, "%s: device %d beyond the %d supported", name,
+                    dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(JBFD_EHIP, "%s: hipGetSymbolAddress: %s", name,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return JBFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+jbfd_status jbfd_project_densify_noalloc(const float *pts_xyz, int64_t n,
+                                         const double cam_from_world[12],
+                                         const jbfd_intrinsics *K,
+                                         const uint8_t *rgb_hwc, int32_t radius,
+                                         float sigma_s, float sigma_r,
+                                         jbfd_precision prec, uint64_t *zbuf,
+                                         float *sparse_depth, uint8_t *sparse_valid,
+                                         float *dense_depth, uint8_t *dense_valid,
+                                         void *stream) {
+    const char *name = "jbfd_project_densify_noalloc";
+    jbfd_status st = check_project_densify(
+        name, pts_xyz, n, cam_from_world, K, rgb_hwc, radius, sigma_s, sigma_r, prec,
+        zbuf, sparse_depth, sparse_valid, dense_depth, dense_valid);
+    if (st != JBFD_OK) return st;
+    // every valid sample is a projected point, so n bounds the lists
+    const size_t need = jbfd::densify_ws_bytes(K->height, K->width, radius, n);
+    if (need > JBFD_NOALLOC_WS_BYTES)
+        return fail(JBFD_ENOSPC,
+                    "%s: the sample lists of a %d x %d image with up to %lld points "
+                    "at radius %d need %zu bytes, more than the %zu bytes built in",
+                    name, K->width, K->height, (long long)n, radius, need,
+                    (size_t)JBFD_NOALLOC_WS_BYTES);
+    void *ws = nullptr;
+    st = scratch_address(name, &ws);
+    if (st != JBFD_OK) return st;
+    return run_project_densify(name, pts_xyz, n, cam_from_world, K, rgb_hwc, radius,
+                               sigma_s, sigma_r, prec, zbuf, sparse_depth,
+                               sparse_valid, dense_depth, dense_valid, ws,
+                               JBFD_NOALLOC_WS_BYTES, stream);
 }
 
 jbfd_status jbfd_zbuf_clear(uint64_t *zbuf, int32_t H, int32_t W, void *stream) {

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_status_strings(L):
     from paper_2601_01210_amd import binding
-    assert L.jbfd_abi_version() == 3
+    assert L.jbfd_abi_version() == 4
     for code in range(5):
         assert L.jbfd_status_string(code)
     assert L.jbfd_status_string(99) == b"unknown status"
@@ -369,3 +369,26 @@ def test_batch_prepare_checks_list_workspaces(L):
     assert prep() == JBFD_ENOSPC
     v.list_ws, v.list_ws_bytes = fake + 4, tables
     assert prep() == JBFD_EINVAL
+
+
+def test_noalloc_rejects_lists_beyond_its_array(L):
+    """jbfd_project_densify_noalloc refuses, before any HIP call, a request
+    whose sample lists may exceed its fixed array (4K image, 2M points,
+    r = 32), and states the sizes; bad arguments are EINVAL as usual."""
+    from paper_2601_01210_amd.binding import (JBFD_EINVAL, JBFD_ENOSPC,
+                                              NOALLOC_WS_BYTES, Intrinsics)
+    pose = (C.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    K = Intrinsics(1000.0, 1000.0, 1920.0, 1080.0, 3840, 2160)
+    args = (fake, 2_000_000, pose, C.byref(K), fake, 32, 6.0, 15.0, 0, fake, fake,
+            fake, fake, fake, None)
+    assert L.jbfd_densify_ws_bytes(2160, 3840, 32, 2_000_000) > NOALLOC_WS_BYTES
+    assert L.jbfd_project_densify_noalloc(*args) == JBFD_ENOSPC
+    msg = L.jbfd_last_error().decode()
+    assert "3840 x 2160" in msg and str(NOALLOC_WS_BYTES) in msg
+    bad = list(args)
+    bad[5] = 33                                   # radius above the maximum
+    assert L.jbfd_project_densify_noalloc(*bad) == JBFD_EINVAL
+    bad = list(args)
+    bad[9] = None                                 # null key buffer
+    assert L.jbfd_project_densify_noalloc(*bad) == JBFD_EINVAL
