@@ -218,14 +218,15 @@ def batched_leg(torch, dev, frames, steps):
            "radius": max_r, "algorithmic_bytes": min_bytes}
     stream = torch.cuda.current_stream(dev)
     for prec in (Precision.FP32, Precision.FP16_RANGE):
-        graphs = []
+        graphs, staged = [], []
         for views, table, _ in sets:
-            batch_run(table, max_r, prec)
-            torch.cuda.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, capture_error_mode="thread_local"):
-                batch_run(table, max_r, prec)
-            graphs.append(g)
+            for staged_run, dst in ((False, graphs), (True, staged)):
+                batch_run(table, max_r, prec, staged=staged_run)
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, capture_error_mode="thread_local"):
+                    batch_run(table, max_r, prec, staged=staged_run)
+                dst.append(g)
         torch.cuda.synchronize()
 
         def per_view(k):
@@ -242,6 +243,8 @@ def batched_leg(torch, dev, frames, steps):
         timings = {}
         for name, fn in (("batched_graph",
                           lambda k: graphs[k % len(graphs)].replay()),
+                         ("staged_graph",
+                          lambda k: staged[k % len(staged)].replay()),
                          ("per_view_calls", per_view)):
             for k in range(5):
                 fn(k)
@@ -255,12 +258,14 @@ def batched_leg(torch, dev, frames, steps):
             timings[name] = ev[0].elapsed_time(ev[1]) / steps
         b, p = timings["batched_graph"], timings["per_view_calls"]
         res[prec.name.lower()] = {
-            "batched_ms": round(b, 4), "per_view_calls_ms": round(p, 4),
+            "batched_ms": round(b, 4),
+            "staged_launches_ms": round(timings["staged_graph"], 4),
+            "per_view_calls_ms": round(p, 4),
             "batched_fhd_frames_per_s": round(px / FHD / (b * 1e-3), 1),
             "per_view_fhd_frames_per_s": round(px / FHD / (p * 1e-3), 1),
             "batched_hbm_frac_algorithmic": round(
                 min_bytes / (b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        del graphs
+        del graphs, staged
     del sets
     torch.cuda.synchronize()
     return res

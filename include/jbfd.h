@@ -22,9 +22,9 @@
  *                      widths (Sec. 4: the filter parameters are trainable
  *                      by backpropagation);
  *   4. jbfd_batch_run - projection + filter for many viewpoints of mixed
- *                      size in one fixed-grid launch sequence that covers
- *                      every view (Sec. 2 processes each viewpoint
- *                      independently);
+ *                      size in one persistent launch that takes work items
+ *                      of every view from a device queue (Sec. 2 processes
+ *                      each viewpoint independently);
  *   5. jbfd_densify_two_stage (with jbfd_pool3, jbfd_restore_merge) - the
  *                      two-stage filter of Sec. 5: a pass at a third of the
  *                      resolution, then a small-radius pass at full size;
@@ -71,7 +71,7 @@
 extern "C" {
 #endif
 
-#define JBFD_ABI_VERSION 4
+#define JBFD_ABI_VERSION 5
 
 /* Largest filter radius: the halo of one 8x8 output block must fit the
  * per-workgroup spatial table in LDS. */
@@ -349,17 +349,30 @@ size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
  * device-side descriptor table into a HOST buffer of
  * jbfd_batch_table_bytes(n_views) bytes (pinned memory lets the copy be
  * asynchronous and captured); the caller copies it to device memory and
- * calls jbfd_batch_run() with that device pointer. jbfd_batch_run launches
- * fixed-size grids (clear, project, decode, with JBFD_BATCH_LISTS list
- * count and list scatter, filter) that read every size
- * from the table, so the launches can be captured once into a HIP graph and
- * replayed for any batch written into the same device table, as long as
- * every radius stays <= the captured max_radius.
+ * calls jbfd_batch_run() with that device pointer. By default
+ * jbfd_batch_run is ONE persistent launch of a fixed grid that takes work
+ * items from device queues in the table: every view's projection chunks,
+ * then every view's key decode chunks, then every view's filter tiles, each
+ * item waiting (bounded) only for the earlier items of its own view, so a
+ * view is filtered while later views are still being decoded. It needs each
+ * view's key buffer to hold only empty keys (UINT64_MAX) on entry: clear a
+ * new buffer once with jbfd_zbuf_clear; every batch run, in either form,
+ * leaves it so (the decode writes the empty key back over each key it
+ * reads). With JBFD_BATCH_STAGED (or JBFD_BATCH_LISTS) the run is instead a
+ * sequence of fixed-grid launches (clear, project, decode, with
+ * JBFD_BATCH_LISTS list count and list scatter, filter), each covering
+ * every view; it clears the keys itself. Either way every size is read from the table on the device,
+ * so the launch(es) can be captured once into a HIP graph and replayed for
+ * any batch written into the same device table, as long as every radius
+ * stays <= the captured max_radius; the one-launch run leaves its queue
+ * reset, so it may also be replayed on an unchanged table.
  *
  * Per view, the work is that of jbfd_project followed by jbfd_densify on
  * the same definitions (with sample lists when the run has
  * JBFD_BATCH_LISTS and the view brings a list workspace, else streaming the
- * halo); outputs are identical to the single-view calls made the same way. Views must not share output, scratch or list buffers.
+ * halo); outputs are identical to the single-view calls made the same way.
+ * Views must not share output, scratch or list buffers, and runs that share
+ * a device table must be ordered (the table holds the run's queue).
  * A list workspace smaller than its tables (jbfd_densify_ws_bytes with no
  * samples) is JBFD_ENOSPC; a block whose list does not fit streams.
  */
@@ -371,7 +384,9 @@ typedef struct jbfd_view {
     const uint8_t *rgb;       /* H*W*3 guide image (device) */
     int32_t radius;           /* 0 .. JBFD_MAX_RADIUS */
     float sigma_s, sigma_r;   /* as jbfd_densify */
-    uint64_t *zbuf;           /* H*W scratch (device) */
+    uint64_t *zbuf;           /* H*W key buffer (device): only empty keys
+                                 on entry of a one-launch run, and after
+                                 every run */
     float *sparse_depth;      /* H*W scratch/output (device) */
     uint8_t *sparse_valid;    /* H*W scratch/output (device) */
     float *dense_depth;       /* H*W output (device) */
@@ -394,14 +409,26 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
                                void *host_table, size_t table_bytes);
 
 /* Run a batch whose table (from jbfd_batch_prepare) is at d_table (device,
- * 8-byte aligned). max_radius bounds every view's radius (it selects the
- * kernel variant and the LDS size). flags: 0, or JBFD_BATCH_LISTS to build
- * the sample lists of the views that bring a list workspace and walk them
- * in the filter (without it every view streams its halo, list workspace or
- * not). Capturable in a HIP graph. */
+ * 8-byte aligned, written by the run: it holds the one-launch queue and an
+ * error word). max_radius bounds every view's radius (it selects the kernel
+ * variant and the LDS size); a view with a larger radius gets zero depth
+ * and mask and sets the error word that jbfd_batch_check reports. flags: 0
+ * (one persistent launch, every view streams its halo), JBFD_BATCH_STAGED
+ * (the same results from a sequence of launches), or JBFD_BATCH_LISTS
+ * (launch sequence that builds the sample lists of the views that bring a
+ * list workspace and walks them in the filter). Capturable in a HIP graph. */
 #define JBFD_BATCH_LISTS 1u
-jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
-                           jbfd_precision prec, uint32_t flags, void *stream);
+#define JBFD_BATCH_STAGED 2u
+jbfd_status jbfd_batch_run(void *d_table, int32_t max_radius, jbfd_precision prec,
+                           uint32_t flags, void *stream);
+
+/* After the runs on a table since its jbfd_batch_prepare have finished on
+ * `stream`: JBFD_OK, or JBFD_EINVAL when a view's radius exceeded the run's
+ * max_radius (that view's outputs are zeros), or JBFD_EHIP when a work item
+ * of the one-launch run gave up waiting (the outputs are not valid). Copies
+ * the table's error word to the host and synchronises `stream`; allocates
+ * nothing. */
+jbfd_status jbfd_batch_check(const void *d_table, void *stream);
 
 /*
  * Two-stage filtering (Sec. 5: a first pass at a third of the resolution

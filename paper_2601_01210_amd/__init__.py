@@ -9,9 +9,10 @@ raise.
 """
 from .binding import (BatchView, JbfdError, Precision,  # noqa: F401
                       abi_version, backproject, backproject_ws_bytes,
-                      batch_run, batch_table_bytes, remove_occluded,
-                      batch_upload, densify, densify_backward,
+                      batch_check, batch_run, batch_table_bytes,
+                      remove_occluded, batch_upload, densify, densify_backward,
                       densify_prepare, densify_two_stage, densify_workspace,
                       densify_ws_bytes, library_path, motion_mask, pool3,
-                      project, project_densify, project_motion, restore_merge,
-                      two_stage_ws_bytes, zbuf_clear)
+                      project, project_densify, project_densify_noalloc,
+                      project_motion, restore_merge, two_stage_ws_bytes,
+                      zbuf_clear)

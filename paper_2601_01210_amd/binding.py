@@ -141,6 +141,8 @@ def lib():
         L.jbfd_batch_prepare.argtypes = [C.POINTER(View), i32, vp, sz]
         L.jbfd_batch_run.restype = C.c_int
         L.jbfd_batch_run.argtypes = [vp, i32, C.c_int, C.c_uint32, vp]
+        L.jbfd_batch_check.restype = C.c_int
+        L.jbfd_batch_check.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -479,7 +481,10 @@ class BatchView:
         Without lists the batch filter streams each block's halo. At small
         radii that is the faster choice for a batch (building the lists of
         eight 720p/1080p views costs more than the walk saves at r = 5); at
-        large radii the list walk is much cheaper than streaming."""
+        large radii the list walk is much cheaper than streaming.
+
+        A new key buffer is cleared to empty keys (jbfd_zbuf_clear), as the
+        one-launch batch run requires on entry; every batch run leaves it so."""
         torch = _torch()
         dev = device if device is not None else self.points.device
         hw = (self.height, self.width)
@@ -488,7 +493,7 @@ class BatchView:
             self.list_ws = densify_workspace(self.height, self.width, int(r),
                                              max(int(self.points.shape[0]), 1), dev)
         if self.zbuf is None:
-            self.zbuf = torch.empty(hw, dtype=torch.int64, device=dev)
+            self.zbuf = zbuf_clear(torch.empty(hw, dtype=torch.int64, device=dev))
         if self.sparse_depth is None:
             self.sparse_depth = torch.empty(hw, dtype=torch.float32, device=dev)
         if self.sparse_valid is None:
@@ -572,19 +577,30 @@ def batch_upload(views: Sequence[BatchView], table=None, host=None):
     return table, host
 
 
-JBFD_BATCH_LISTS = 1
+JBFD_BATCH_LISTS, JBFD_BATCH_STAGED = 1, 2
 
 
 def batch_run(table, max_radius: int, precision: Precision = Precision.FP32,
-              lists: bool = False):
-    """Enqueue jbfd_batch_run on the current stream (graph-capturable).
-    ``lists``: build and walk the sample lists of the views that carry a
-    list workspace (JBFD_BATCH_LISTS); otherwise every view streams."""
+              lists: bool = False, staged: bool = False):
+    """Enqueue jbfd_batch_run on the current stream (graph-capturable): one
+    persistent launch by default. ``staged``: the same work as a sequence of
+    launches (JBFD_BATCH_STAGED); ``lists``: a launch sequence that builds
+    and walks the sample lists of the views that carry a list workspace
+    (JBFD_BATCH_LISTS); otherwise every view streams."""
     torch = _torch()
     _need(table, torch.uint8, None, "table")
-    _check(lib().jbfd_batch_run(_ptr(table), int(max_radius), int(precision),
-                                JBFD_BATCH_LISTS if lists else 0,
+    flags = (JBFD_BATCH_LISTS if lists else 0) | (JBFD_BATCH_STAGED if staged else 0)
+    _check(lib().jbfd_batch_run(_ptr(table), int(max_radius), int(precision), flags,
                                 _stream(table.device)))
+
+
+def batch_check(table):
+    """Synchronise the current stream and raise JbfdError if a run on this
+    table since its preparation met a view whose radius exceeded the run's
+    max_radius (JBFD_EINVAL) or gave up a wait (JBFD_EHIP)."""
+    torch = _torch()
+    _need(table, torch.uint8, None, "table")
+    _check(lib().jbfd_batch_check(_ptr(table), _stream(table.device)))
 
 
 # ---------------------------------------------------------------------------

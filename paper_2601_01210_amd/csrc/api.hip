@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <mutex>
 
@@ -574,7 +575,8 @@ jbfd_status jbfd_project_motion(const float *pts_xyz, int64_t n,
 
 size_t jbfd_batch_table_bytes(int32_t n_views) {
     if (n_views < 1) return 0;
-    return sizeof(jbfd::BatchHeader) + (size_t)n_views * sizeof(jbfd::BatchView);
+    return jbfd::batch_counters_offset(n_views) +
+           (size_t)n_views * sizeof(jbfd::BatchCounters);
 }
 
 jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
@@ -588,6 +590,8 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
     jbfd::BatchView *out = reinterpret_cast<jbfd::BatchView *>(
         static_cast<unsigned char *>(host_table) + sizeof(jbfd::BatchHeader));
     int64_t tiles = 0, px_chunks = 0, pt_chunks = 0, units = 0;
+    int64_t fpx = 0, fpt = 0, ftile = 0;   // items of the one-launch run
+    int32_t max_radius = 0;
     for (int32_t v = 0; v < n_views; ++v) {
         const jbfd_view &x = views[v];
         if (!x.rgb || !x.zbuf || !x.sparse_depth || !x.sparse_valid ||
@@ -628,11 +632,20 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
         b.n_tiles = b.tiles_x * ((x.K.height + jbfd::kTileEdge - 1) / jbfd::kTileEdge);
         b.tile_off = (int32_t)tiles;
         tiles += b.n_tiles;
+        const int64_t npix = (int64_t)x.K.width * x.K.height;
         b.px_chunk_off = (int32_t)px_chunks;
-        px_chunks += ((int64_t)x.K.width * x.K.height + jbfd::kBatchChunk - 1) /
-                     jbfd::kBatchChunk;
+        px_chunks += (npix + jbfd::kBatchChunk - 1) / jbfd::kBatchChunk;
         b.pt_chunk_off = (int32_t)pt_chunks;
         pt_chunks += (x.n_points + jbfd::kBatchChunk - 1) / jbfd::kBatchChunk;
+        // one-launch queue: projection chunks, decode chunks, filter items
+        b.fpx_off = (int32_t)fpx;
+        fpx += (npix + jbfd::kFusedPxChunk - 1) / jbfd::kFusedPxChunk;
+        b.fpt_off = (int32_t)fpt;
+        fpt += (x.n_points + jbfd::kFusedPtChunk - 1) / jbfd::kFusedPtChunk;
+        b.ftile_off = (int32_t)ftile;
+        ftile += (b.n_tiles + jbfd::kFusedTiles - 1) / jbfd::kFusedTiles;
+        b.pad_ = 0;
+        if (x.radius > max_radius) max_radius = x.radius;
         // sample lists (as jbfd_densify with a workspace)
         const jbfd::ListLayout L = jbfd::list_layout(x.K.height, x.K.width);
         b.recs = nullptr;
@@ -658,8 +671,10 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
                 units += (int64_t)L.n_groups * L.n_bands;
             }
         }
-        if (tiles >= ((int64_t)1 << 31) || px_chunks >= ((int64_t)1 << 31) ||
-            pt_chunks >= ((int64_t)1 << 31) || units >= ((int64_t)1 << 31))
+        // the queues number every item in one int32 (well below 2^30 items
+        // when the launch-sequence counts, which are larger, are)
+        if (tiles >= ((int64_t)1 << 30) || px_chunks >= ((int64_t)1 << 30) ||
+            pt_chunks >= ((int64_t)1 << 30) || units >= ((int64_t)1 << 30))
             return fail(JBFD_EINVAL, "batch: too many tiles or chunks");
     }
     hdr->n_views = n_views;
@@ -667,24 +682,57 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
     hdr->px_chunks = (int32_t)px_chunks;
     hdr->pt_chunks = (int32_t)pt_chunks;
     hdr->list_units = (int32_t)units;
+    hdr->max_radius = max_radius;
+    hdr->fpx_chunks = (int32_t)fpx;
+    hdr->fpt_chunks = (int32_t)fpt;
+    hdr->ftile_items = (int32_t)ftile;
+    hdr->exited = 0;
+    hdr->error = 0;
     hdr->pad_ = 0;
+    unsigned char *state = static_cast<unsigned char *>(host_table) +
+                           jbfd::batch_queues_offset(n_views);
+    memset(state, 0, jbfd_batch_table_bytes(n_views) - jbfd::batch_queues_offset(n_views));
     return ok();
 }
 
-jbfd_status jbfd_batch_run(const void *d_table, int32_t max_radius,
-                           jbfd_precision prec, uint32_t flags, void *stream) {
+jbfd_status jbfd_batch_run(void *d_table, int32_t max_radius, jbfd_precision prec,
+                           uint32_t flags, void *stream) {
     if (!d_table || ((uintptr_t)d_table & 7))
         return fail(JBFD_EINVAL, "jbfd_batch_run: null or misaligned table");
     if (max_radius < 0 || max_radius > JBFD_MAX_RADIUS)
         return fail(JBFD_EINVAL, "jbfd_batch_run: max_radius %d", max_radius);
     if (prec != JBFD_FP32 && prec != JBFD_FP16_RANGE)
         return fail(JBFD_EINVAL, "jbfd_batch_run: unknown precision %d", (int)prec);
-    if (flags & ~JBFD_BATCH_LISTS)
+    if (flags & ~(JBFD_BATCH_LISTS | JBFD_BATCH_STAGED))
         return fail(JBFD_EINVAL, "jbfd_batch_run: unknown flags 0x%x", flags);
-    return hip_status(jbfd::launch_batch(d_table, max_radius,
-                                         (flags & JBFD_BATCH_LISTS) != 0, prec,
-                                         (hipStream_t)stream),
-                      "jbfd_batch_run");
+    hipError_t e;
+    if (flags & (JBFD_BATCH_LISTS | JBFD_BATCH_STAGED))
+        e = jbfd::launch_batch(d_table, max_radius, (flags & JBFD_BATCH_LISTS) != 0, prec,
+                               (hipStream_t)stream);
+    else
+        e = jbfd::launch_batch_fused(d_table, max_radius, prec, (hipStream_t)stream);
+    return hip_status(e, "jbfd_batch_run");
+}
+
+jbfd_status jbfd_batch_check(const void *d_table, void *stream) {
+    if (!d_table || ((uintptr_t)d_table & 7))
+        return fail(JBFD_EINVAL, "jbfd_batch_check: null or misaligned table");
+    uint32_t err = 0;
+    const unsigned char *src = static_cast<const unsigned char *>(d_table) +
+                               offsetof(jbfd::BatchHeader, error);
+    hipError_t e = hipMemcpyAsync(&err, src, sizeof err, hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_status(e, "jbfd_batch_check");
+    if (err & jbfd::kBatchErrRadius)
+        return fail(JBFD_EINVAL,
+                    "jbfd_batch_check: a view's radius exceeded the max_radius of the "
+                    "run; its outputs were set to zero");
+    if (err & jbfd::kBatchErrWait)
+        return fail(JBFD_EHIP,
+                    "jbfd_batch_check: a work item gave up waiting for the items it "
+                    "depends on; the batch's outputs are not valid");
+    return ok();
 }
 
 }  // extern "C"

@@ -56,6 +56,7 @@
 // The fraction of (pixel, halo sample) pairs that fall inside the window is
 // (2r+1)^2/(2r+8)^2 (66% at r = 15).
 #include "filter_common.hpp"
+#include "project_common.hpp"
 
 namespace jbfd {
 
@@ -758,11 +759,24 @@ hipError_t launch_project_densify(const float *pts, int64_t n, const Pose &pose,
 
 namespace jbfd {
 
+// A tile of a view whose radius exceeds the launch's table bound: its
+// outputs are zero (no valid pixel) and the batch's error word records it.
+__device__ inline void refuse_tile(BatchHeader *hdr, const BatchView &v, int tx, int ty) {
+    const int px = tx * kTile + (int)(threadIdx.x & 15);
+    const int py = ty * kTile + (int)(threadIdx.x >> 4);
+    if (px < v.W && py < v.H) {
+        const int64_t p = (int64_t)py * v.W + px;
+        v.out[p] = 0.0f;
+        v.mask[p] = 0;
+    }
+    if (threadIdx.x == 0) atomicOr(&hdr->error, kBatchErrRadius);
+}
+
 // Filter tiles of every view of a batch: a fixed grid walks the flattened
 // tile space (views back to back); each workgroup finds its view by a
 // binary search of the table's tile offsets (wave-uniform scalar loads).
 template <int RMAX, int PREC>
-__global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restrict__ hdr,
+__global__ __launch_bounds__(256) void k_batch_filter(BatchHeader *__restrict__ hdr,
                                                       const BatchView *__restrict__ views,
                                                       bool use_lists) {
     __shared__ FilterShared<RMAX> sh;
@@ -777,6 +791,10 @@ __global__ __launch_bounds__(256) void k_batch_filter(const BatchHeader *__restr
         const BatchView &v = views[lo];
         const int local = t - v.tile_off;
         const int ty = local / v.tiles_x, tx = local - ty * v.tiles_x;
+        if (v.radius > RMAX) {   // uniform: the table would not fit
+            refuse_tile(hdr, v, tx, ty);
+            continue;
+        }
         const FilterParams fp{v.radius, v.kr, v.ks};
         const bool rebuild = fp.radius != cur_r || fp.ks != cur_ks;  // uniform
         if (rebuild && cur_r >= 0) __syncthreads();  // old table no longer read
@@ -828,7 +846,7 @@ hipError_t launch_batch_lists(const BatchHeader *hdr, const BatchView *views,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
+hipError_t launch_batch_filter(BatchHeader *hdr, const BatchView *views,
                                int32_t max_radius, jbfd_precision prec,
                                bool use_lists, hipStream_t s) {
     const int grid = 2048;   // 8 workgroups per CU
@@ -843,6 +861,284 @@ hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
         else
             k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr,
                                                                                 views, use_lists);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// the whole batch in one persistent launch
+// ---------------------------------------------------------------------------
+//
+// The key buffers hold only empty keys on entry (every batch run leaves
+// them so: its decode writes the empty key back over each key it reads), so
+// the run has no clearing pass. Work items, numbered in this order (each
+// part view by view):
+//   [0, P)          projection chunks (kFusedPtChunk points),
+//   [P, P + C)      decode chunks (kFusedPxChunk pixels),
+//   [P + C, ...)    filter items (kFusedTiles tiles of one row run each).
+// An item waits only for earlier items of its own view: a decode chunk for
+// the view's projection chunks, a filter item for its decode chunks. Every
+// decode comes before every filter item in every queue, so a filter item
+// never waits on a decode that some queue has not reached because its
+// workgroups are held by earlier filter items (with each view's decode just
+// before its own filter items, workgroups averaged 0.34 ms of waiting on the
+// eight-view batch). The items are dealt to kQueues queues in turns of
+// kQueueRun consecutive items; workgroup w takes the items of queue
+// w % kQueues in increasing order (one atomic per item on that queue's
+// counter: one shared counter for every item measured 0.4 ms of hand-outs
+// alone on the eight-view batch, the atomics on one address being served
+// one after another). A workgroup claims its next item while it works on
+// the current one and starts it only after. So the lowest unfinished item,
+// whose queue has handed out every earlier item of its own, is held by a
+// workgroup of that queue that works on it or is free to take it, and it
+// depends only on finished items: the queues advance and every wait ends as
+// long as each queue has a resident workgroup (the first kQueues workgroups
+// of the grid cover every queue).
+//
+// Data passes between items of different workgroups, which may sit on
+// different XCDs with separate L2 caches. The keys are lowered by atomicMin
+// (performed at the memory side, coherent across XCDs) and read back by
+// the decode with relaxed agent-scope loads. The decode writes the sparse
+// depth and mask with write-through stores (relaxed agent-scope atomic
+// stores), each cache line by one decode chunk; the filter then reads them
+// with ordinary loads: no L2
+// holds a line of them from before (the launch starts with no stale lines,
+// as every launch does, and nothing reads a view's sparse image before its
+// decode is published), so every L2 fetches them fresh. The decode's
+// write-back of empty keys is read only by the next launch. An item is
+// published when every wave has waited for its own stores and atomics to
+// complete (s_waitcnt vmcnt(0)) and then one thread increments the view's
+// counter; a dependent item polls the counter with coherent loads. No L2
+// write-back or invalidation is needed (an agent-scope release or acquire
+// fence would write back or invalidate the whole L2 once per item).
+//
+// Waits are bounded: after kSpinLimit polls the item sets kBatchErrWait in
+// the header and runs anyway, so the launch always ends (its results are
+// then not to be trusted, and jbfd_batch_check reports it). The last
+// workgroup to finish resets the queues and the counters, so a captured
+// launch can be replayed on the same table.
+
+constexpr int kSpinLimit = 1 << 22;   // polls (about 0.1 s) before giving up
+
+__device__ inline void store_coherent(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_coherent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_coherent(float *p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_coherent(uint8_t *p, uint8_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t load_coherent(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t load_coherent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every vector memory access this wave has issued has completed (stores and
+// atomics acknowledged); the clobber keeps the compiler from moving memory
+// accesses across the wait.
+__device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The workgroup's item is done: count it for its view.
+__device__ inline void publish(uint32_t *counter) {
+    wait_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(counter, 1u);
+}
+
+// Wait until *counter reaches need (thread 0 polls, the workgroup waits at
+// the barrier). False when the wait gave up.
+__device__ inline bool await_count(const uint32_t *counter, uint32_t need,
+                                   BatchHeader *hdr, int &s_ok) {
+    if (threadIdx.x == 0) {
+        int polls = 0;
+        while (load_coherent(counter) < need) {
+            if (++polls > kSpinLimit) {
+                atomicOr(&hdr->error, kBatchErrWait);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        s_ok = polls <= kSpinLimit;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__device__ inline int pixel_items(const BatchView &v) {
+    return (int)(((int64_t)v.W * v.H + kFusedPxChunk - 1) / kFusedPxChunk);
+}
+
+__device__ inline int point_items(const BatchView &v) {
+    return (int)((v.n_pts + kFusedPtChunk - 1) / kFusedPtChunk);
+}
+
+// points [c kFusedPtChunk, (c + 1) kFusedPtChunk) into the key image
+__device__ inline void project_chunk(const BatchView &v, int c) {
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(v.zbuf);
+    const int64_t i0 = (int64_t)c * kFusedPtChunk + threadIdx.x;
+    // not unrolled: several projections in flight would raise the register
+    // count of the whole kernel above the filter's
+#pragma unroll 1
+    for (int j = 0; j < kFusedPtChunk / 256; ++j) {
+        const int64_t i = i0 + 256 * j;
+        if (i >= v.n_pts) break;
+        unsigned long long key;
+        int64_t pix;
+        if (project_one(v.pts, i, v.pose, v.fx, v.fy, v.cx, v.cy, v.W, v.H, key, pix))
+            atomicMin(keys + pix, key);
+    }
+}
+
+// keys of the chunk's pixels -> sparse depth (0 where empty) and 0/1 mask,
+// four consecutive pixels per thread and pass; the empty key is written
+// back over each key read (ordinary stores: only the next launch reads them)
+__device__ inline void decode_chunk(const BatchView &v, int c) {
+    const int64_t npix = (int64_t)v.W * v.H;
+    const bool vec = ((reinterpret_cast<uintptr_t>(v.sd) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(v.sv) & 3) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(v.zbuf) & 15) == 0);
+    for (int pass = 0; pass < kFusedPxChunk / 1024; ++pass) {
+        const int64_t p0 = (int64_t)c * kFusedPxChunk + 1024 * pass + 4 * (int64_t)threadIdx.x;
+        if (vec && p0 + 4 <= npix) {
+            uint32_t d[4], m = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t key = load_coherent(v.zbuf + p0 + k);
+                const bool hit = key != kEmptyKey;
+                d[k] = hit ? (uint32_t)(key >> 32) : 0u;   // the bits of float Z, or +0
+                m |= (uint32_t)hit << (8 * k);
+            }
+            // (two 8-byte stores: a 16-byte store with this cache policy
+            // exists only as inline assembly, whose data registers the
+            // compiler would not protect until the store has read them)
+            store_coherent(reinterpret_cast<uint64_t *>(v.sd + p0),
+                           (uint64_t)d[0] | ((uint64_t)d[1] << 32));
+            store_coherent(reinterpret_cast<uint64_t *>(v.sd + p0 + 2),
+                           (uint64_t)d[2] | ((uint64_t)d[3] << 32));
+            store_coherent(reinterpret_cast<uint32_t *>(v.sv + p0), m);
+            const ulonglong2 e = make_ulonglong2(kEmptyKey, kEmptyKey);
+            *reinterpret_cast<ulonglong2 *>(v.zbuf + p0) = e;
+            *reinterpret_cast<ulonglong2 *>(v.zbuf + p0 + 2) = e;
+        } else {
+            for (int64_t p = p0; p < npix && p < p0 + 4; ++p) {
+                const uint64_t key = load_coherent(v.zbuf + p);
+                const bool hit = key != kEmptyKey;
+                store_coherent(v.sd + p, hit ? __uint_as_float((uint32_t)(key >> 32)) : 0.0f);
+                store_coherent(v.sv + p, (uint8_t)hit);
+                v.zbuf[p] = kEmptyKey;
+            }
+        }
+    }
+}
+
+// The k-th item of queue q: queues take turns of kQueueRun consecutive
+// items, so each queue's items rise with k and keep neighbours together.
+__device__ inline int queue_item(int q, uint32_t k) {
+    const int turn = (int)(k / kQueueRun), within = (int)(k % kQueueRun);
+    return (turn * kQueues + q) * kQueueRun + within;
+}
+
+// Six waves per SIMD at RMAX = 16: 80 registers, none spilled (at eight, as
+// the staged filter kernel has, 14 registers of loop state go to scratch
+// and the eight-view batch took 0.275 ms; at seven, 2 and 0.258 ms; at six
+// 0.253 ms). The LDS of the RMAX = 32 table allows four.
+template <int RMAX, int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RMAX <= 16 ? 6 : 4)))
+void k_batch_fused(BatchHeader *__restrict__ hdr, const BatchView *__restrict__ views) {
+    __shared__ FilterShared<RMAX> sh;
+    __shared__ int s_item, s_ok;
+    const int n_views = hdr->n_views;
+    unsigned char *state =
+        reinterpret_cast<unsigned char *>(const_cast<BatchView *>(views) + n_views);
+    BatchLine *queues = reinterpret_cast<BatchLine *>(state);
+    BatchCounters *cnt = reinterpret_cast<BatchCounters *>(state + kQueues * sizeof(BatchLine));
+    const int C = hdr->fpx_chunks, P = hdr->fpt_chunks;
+    const int total = P + C + hdr->ftile_items;
+    const int q = (int)(blockIdx.x % kQueues);
+    uint32_t *turn = &queues[q].n;
+    int cur_r = -1;       // radius and sigma_s of the spatial table in LDS
+    float cur_ks = 0.0f;
+    if (threadIdx.x == 0) s_item = queue_item(q, atomicAdd(turn, 1u));
+    __syncthreads();
+    int item = s_item;
+    while (item < total) {
+        int next = 0;
+        if (threadIdx.x == 0) next = queue_item(q, atomicAdd(turn, 1u));
+        if (item < P) {
+            const int v = batch_view_of<&BatchView::fpt_off>(views, n_views, item);
+            project_chunk(views[v], item - views[v].fpt_off);
+            publish(&cnt[v].projected.n);
+        } else if (item < P + C) {
+            const int c = item - P;
+            const int v = batch_view_of<&BatchView::fpx_off>(views, n_views, c);
+            const BatchView &bv = views[v];
+            await_count(&cnt[v].projected.n, point_items(bv), hdr, s_ok);
+            decode_chunk(bv, c - bv.fpx_off);
+            publish(&cnt[v].decoded.n);
+        } else {
+            const int t = item - P - C;
+            const int v = batch_view_of<&BatchView::ftile_off>(views, n_views, t);
+            const BatchView &bv = views[v];
+            const int t0 = kFusedTiles * (t - bv.ftile_off);
+            if (bv.radius > RMAX) {   // uniform: the table would not fit
+                for (int lt = t0; lt < min(t0 + kFusedTiles, bv.n_tiles); ++lt)
+                    refuse_tile(hdr, bv, lt % bv.tiles_x, lt / bv.tiles_x);
+            } else {
+                await_count(&cnt[v].decoded.n, pixel_items(bv), hdr, s_ok);
+                const FilterParams fp{bv.radius, bv.kr, bv.ks};
+                // the previous item ended at a barrier, so its table reads
+                // are over before a rebuild; the tiles of one item share it
+                bool rebuild = fp.radius != cur_r || fp.ks != cur_ks;
+                const ListArgs none{nullptr, nullptr, 0};
+                for (int lt = t0; lt < min(t0 + kFusedTiles, bv.n_tiles); ++lt) {
+                    filter_tile<RMAX, PREC>(bv.sd, bv.sv, bv.rgb, bv.H, bv.W, fp, none,
+                                            lt % bv.tiles_x, lt / bv.tiles_x, bv.out,
+                                            bv.mask, nullptr, sh, rebuild);
+                    rebuild = false;
+                }
+                cur_r = fp.radius;
+                cur_ks = fp.ks;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = next;
+        __syncthreads();
+        item = s_item;
+    }
+    // the last workgroup out resets the queues and counters for the next
+    // run on this table
+    if (threadIdx.x == 0 && atomicAdd(&hdr->exited, 1u) == gridDim.x - 1) {
+        for (int k = 0; k < kQueues; ++k) store_coherent(&queues[k].n, 0u);
+        for (int v = 0; v < n_views; ++v) {
+            store_coherent(&cnt[v].projected.n, 0u);
+            store_coherent(&cnt[v].decoded.n, 0u);
+        }
+        store_coherent(&hdr->exited, 0u);
+    }
+}
+
+hipError_t launch_batch_fused(void *d_table, int32_t max_radius, jbfd_precision prec,
+                              hipStream_t s) {
+    BatchHeader *hdr = static_cast<BatchHeader *>(d_table);
+    const BatchView *views = reinterpret_cast<const BatchView *>(
+        static_cast<const unsigned char *>(d_table) + sizeof(BatchHeader));
+    const int grid = 2048;   // eight workgroups per CU
+    if (max_radius <= 16) {
+        if (prec == JBFD_FP32)
+            k_batch_fused<16, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views);
+        else
+            k_batch_fused<16, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr, views);
+    } else {
+        if (prec == JBFD_FP32)
+            k_batch_fused<JBFD_MAX_RADIUS, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views);
+        else
+            k_batch_fused<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr, views);
     }
     return hipGetLastError();
 }

@@ -279,6 +279,8 @@ __device__ inline uint32_t rec_table_word(int xrel, int y, int ts) {
     return 4u * ((uint32_t)xrel + (uint32_t)ts * (uint32_t)y);
 }
 
+// Walks the valid samples of one 8x8 output block: the sample lists, or the
+// halo streamed from the images.
 struct BlockWalker {
     const float *D;
     const uint8_t *B;

@@ -96,10 +96,27 @@ struct BatchView {
     int64_t capacity;       // records the workspace holds
     int32_t n_strips, n_groups, n_bands;
     int32_t unit_off;       // exclusive prefix of list units over the views
+    // one-launch run: exclusive prefixes over the views of its decode chunks
+    // (kFusedPxChunk pixels), its projection chunks (kFusedPtChunk points)
+    // and its filter items (kFusedTiles tiles)
+    int32_t fpx_off;
+    int32_t fpt_off;
+    int32_t ftile_off;
+    int32_t pad_;
 };
 
-// Elements (pixels or points) one workgroup handles per batch chunk.
+// Elements (pixels or points) one workgroup handles per chunk of the
+// launch-sequence batch.
 constexpr int kBatchChunk = 1024;
+
+// Work items of the one-launch batch: large enough that handing them out
+// costs little next to their work (each hand-out is an atomic on a shared
+// counter), small enough that 2048 workgroups share them evenly.
+constexpr int kFusedPxChunk = 2048;   // pixels per decode item
+constexpr int kFusedPtChunk = 512;    // points per projection item
+constexpr int kFusedTiles = 4;        // filter tiles per item (one row run)
+constexpr int kQueues = 16;           // work queues, workgroup w uses w % kQueues
+constexpr int kQueueRun = 4;          // consecutive items per queue turn
 
 struct BatchHeader {
     int32_t n_views;
@@ -107,8 +124,43 @@ struct BatchHeader {
     int32_t px_chunks;
     int32_t pt_chunks;
     int32_t list_units;     // list units of every view with lists
-    int32_t pad_;           // keeps the views 8-byte aligned
+    int32_t max_radius;     // largest radius over the views
+    int32_t fpx_chunks;     // one-launch run: decode items
+    int32_t fpt_chunks;     //   projection items
+    int32_t ftile_items;    //   filter items
+    // Written by the one-launch run (zero in a freshly prepared table, and
+    // reset to zero by the last workgroup of every run, except `error`).
+    uint32_t exited;        // workgroups that have finished
+    uint32_t error;         // kBatchErr* bits of the runs since preparation
+    uint32_t pad_;
 };
+
+// error bits of a batch run
+constexpr uint32_t kBatchErrRadius = 1;   // a view's radius exceeds the launch's
+                                          // bound: its outputs are zeros
+constexpr uint32_t kBatchErrWait = 2;     // a work item gave up waiting for the
+                                          // items it depends on
+
+// One-launch run state after the views in the table (device-written, zero
+// between runs): the next turn of each work queue and, per view, the items
+// finished per stage. Every counter has a 128-byte line of its own, so
+// atomics on different counters do not queue behind each other.
+struct BatchLine {
+    uint32_t n;
+    uint32_t pad_[31];
+};
+
+struct BatchCounters {
+    BatchLine projected, decoded;
+};
+
+inline size_t batch_queues_offset(int32_t n_views) {
+    return sizeof(BatchHeader) + (size_t)n_views * sizeof(BatchView);
+}
+
+inline size_t batch_counters_offset(int32_t n_views) {
+    return batch_queues_offset(n_views) + kQueues * sizeof(BatchLine);
+}
 
 // Last view v with views[v].*field <= c (the fields are exclusive prefixes,
 // so v is the view that owns chunk or tile c). Wave-uniform arguments give
@@ -171,10 +223,13 @@ hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *swee
 
 hipError_t launch_batch_lists(const BatchHeader *hdr, const BatchView *views,
                               hipStream_t s);
-hipError_t launch_batch(const void *d_table, int32_t max_radius, bool use_lists,
+hipError_t launch_batch(void *d_table, int32_t max_radius, bool use_lists,
                         jbfd_precision prec, hipStream_t s);
-hipError_t launch_batch_filter(const BatchHeader *hdr, const BatchView *views,
+hipError_t launch_batch_filter(BatchHeader *hdr, const BatchView *views,
                                int32_t max_radius, jbfd_precision prec,
                                bool use_lists, hipStream_t s);
+// the whole batch in one persistent launch (streaming filter)
+hipError_t launch_batch_fused(void *d_table, int32_t max_radius, jbfd_precision prec,
+                              hipStream_t s);
 
 }  // namespace jbfd

@@ -23,7 +23,7 @@
 // read + 5HW written by the decode.
 #include <type_traits>
 
-#include "jbfd_internal.hpp"
+#include "project_common.hpp"
 
 namespace jbfd {
 
@@ -50,43 +50,6 @@ __global__ __launch_bounds__(256) void k_fill_keys(uint64_t *__restrict__ keys,
             }
         }
     }
-}
-
-// Project point i; false if it is culled. Otherwise key and pixel index.
-__device__ inline bool project_one(const float *__restrict__ pts, int64_t i,
-                                   const double *__restrict__ m, double fx,
-                                   double fy, double cx, double cy, int32_t w,
-                                   int32_t h, unsigned long long &key,
-                                   int64_t &pix) {
-    const double x = (double)pts[3 * i + 0];
-    const double y = (double)pts[3 * i + 1];
-    const double z = (double)pts[3 * i + 2];
-    // each row summed left to right; no contraction into FMA
-    double X = m[0] * x;
-    X = X + m[1] * y;
-    X = X + m[2] * z;
-    X = X + m[3];
-    double Y = m[4] * x;
-    Y = Y + m[5] * y;
-    Y = Y + m[6] * z;
-    Y = Y + m[7];
-    double Z = m[8] * x;
-    Z = Z + m[9] * y;
-    Z = Z + m[10] * z;
-    Z = Z + m[11];
-    if (!(Z > 0.0) || !__builtin_isfinite(Z)) return false;
-    const double u = fx * (X / Z) + cx;
-    const double v = fy * (Y / Z) + cy;
-    if (!(u >= 0.0 && u < (double)w)) return false;
-    if (!(v >= 0.0 && v < (double)h)) return false;
-    const int64_t col = (int64_t)__builtin_floor(u);
-    const int64_t row = (int64_t)__builtin_floor(v);
-    const float zf = (float)Z;
-    if (zf == 0.0f || __builtin_isinf(zf)) return false;
-    key = ((unsigned long long)__float_as_uint(zf) << 32) |
-          (unsigned long long)(uint32_t)i;
-    pix = row * w + col;
-    return true;
 }
 
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ pts,
@@ -237,9 +200,11 @@ __global__ __launch_bounds__(256) void k_batch_decode(const BatchHeader *__restr
         const int64_t npix = (int64_t)bv.W * bv.H;
         const int64_t p0 = (int64_t)(c - bv.px_chunk_off) * kBatchChunk +
                            4 * (int64_t)threadIdx.x;
+        // the empty key is written back: every batch run leaves its key
+        // buffers empty, as the one-launch run requires them on entry
         if (p0 < npix)
-            decode4<false>(bv.zbuf, npix, p0, decode_vec_ok(bv.zbuf, bv.sd, bv.sv),
-                    bv.sd, bv.sv);
+            decode4<true>(bv.zbuf, npix, p0, decode_vec_ok(bv.zbuf, bv.sd, bv.sv),
+                          bv.sd, bv.sv);
     }
 }
 
@@ -293,9 +258,9 @@ hipError_t launch_project_motion(const float *pts, int64_t n, const int8_t *swee
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const void *d_table, int32_t max_radius, bool use_lists,
+hipError_t launch_batch(void *d_table, int32_t max_radius, bool use_lists,
                         jbfd_precision prec, hipStream_t s) {
-    const BatchHeader *hdr = static_cast<const BatchHeader *>(d_table);
+    BatchHeader *hdr = static_cast<BatchHeader *>(d_table);
     const BatchView *views = reinterpret_cast<const BatchView *>(
         static_cast<const unsigned char *>(d_table) + sizeof(BatchHeader));
     const int grid = 2048;   // eight workgroups per CU, striding over chunks

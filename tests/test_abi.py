@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_status_strings(L):
     from paper_2601_01210_amd import binding
-    assert L.jbfd_abi_version() == 4
+    assert L.jbfd_abi_version() == 5
     for code in range(5):
         assert L.jbfd_status_string(code)
     assert L.jbfd_status_string(99) == b"unknown status"
@@ -257,7 +257,9 @@ def test_batch_run_rejects_bad_arguments(L):
     assert L.jbfd_batch_run(fake, 33, 0, 0, None) == JBFD_EINVAL
     assert L.jbfd_batch_run(fake, -1, 0, 0, None) == JBFD_EINVAL
     assert L.jbfd_batch_run(fake, 5, 7, 0, None) == JBFD_EINVAL
-    assert L.jbfd_batch_run(fake, 5, 0, 2, None) == JBFD_EINVAL    # unknown flag
+    assert L.jbfd_batch_run(fake, 5, 0, 4, None) == JBFD_EINVAL    # unknown flag
+    assert L.jbfd_batch_check(None, None) == JBFD_EINVAL
+    assert L.jbfd_batch_check(C.c_void_p(0x1004), None) == JBFD_EINVAL
 
 
 def test_two_stage_and_dense_reject_bad_arguments(L):

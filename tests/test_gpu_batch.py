@@ -2,11 +2,12 @@
 
 One batch of uneven views (mixed 1280x720 / 1920x1080, 20k-250k points,
 log-uniform, the small-view scene generator, r=5, sigma_s=3, sigma_r=12)
-runs through the fixed-grid batch kernels. Each view's z-buffer must equal
-the oracle's bit for bit and the single-view jbfd_project's; the mask must
-equal the oracle's; FP32 depth must agree with the FP64 oracle to 1e-5
-relative and be bit-identical to the single-view jbfd_densify (same tile
-body, same arithmetic). The FP16 range-weight form runs on the same batch,
+runs as one persistent launch (and, compared bit for bit, as the staged
+launch sequence). Each view's sparse depth and mask (the z-buffer's result)
+must equal the oracle's bit for bit, with the key buffer left empty; the
+dense mask must equal the oracle's; FP32 depth must agree with the FP64
+oracle to 1e-5 relative and be bit-identical to the single-view
+jbfd_densify (same tile body, same arithmetic). The FP16 range-weight form runs on the same batch,
 side by side: its mask must equal the oracle's, every valid pixel must lie
 within the per-pixel bound of FP16 weights (fp16_check), and max / p99.9 /
 mean in mm are printed per view with every pixel above 1 mm named with its
@@ -66,12 +67,23 @@ def _views(torch, dev, frames, **over):
     return vs
 
 
-def _run(torch, views, precision, lists=False):
+def _run(torch, views, precision, lists=False, staged=False, max_radius=None):
     from paper_2601_01210_amd import batch_run, batch_upload
     table, host = batch_upload(views)
-    batch_run(table, max(v.radius for v in views), precision, lists=lists)
+    r = max(v.radius for v in views) if max_radius is None else max_radius
+    batch_run(table, r, precision, lists=lists, staged=staged)
     torch.cuda.synchronize()
     return table, host
+
+
+def _same_outputs(torch, a, b, what):
+    assert torch.equal(a.zbuf, b.zbuf), what
+    assert torch.equal(a.sparse_depth.view(torch.int32),
+                       b.sparse_depth.view(torch.int32)), what
+    assert torch.equal(a.sparse_valid, b.sparse_valid), what
+    assert torch.equal(a.dense_depth.view(torch.int32),
+                       b.dense_depth.view(torch.int32)), what
+    assert torch.equal(a.dense_valid, b.dense_valid), what
 
 
 def _zkeys(t):
@@ -86,7 +98,9 @@ def test_batch_fp32_matches_oracle_and_single_views(tdev, frames, refs):
           flush=True)
     _run(torch, views, Precision.FP32)
     for k, (v, (z, d, b, ref, m)) in enumerate(zip(views, refs)):
-        np.testing.assert_array_equal(_zkeys(v.zbuf), z)
+        # the run leaves its key buffer empty (the decode writes the empty
+        # key back); the z-buffer's result is the sparse depth and mask
+        assert np.all(_zkeys(v.zbuf) == np.uint64(2 ** 64 - 1))
         np.testing.assert_array_equal(v.sparse_valid.cpu().numpy(), b)
         np.testing.assert_array_equal(v.sparse_depth.cpu().numpy(),
                                       d.astype(np.float32))
@@ -151,7 +165,9 @@ def test_batch_mixed_filters_and_degenerate_views(tdev):
                              v.height)
         so, sm = densify(ds, bs, v.rgb, r, ss, sr, ws=None)
         torch.cuda.synchronize()
-        assert torch.equal(zs, v.zbuf), k
+        assert torch.equal(ds.view(torch.int32), v.sparse_depth.view(torch.int32)), k
+        assert torch.equal(bs, v.sparse_valid), k
+        assert bool((v.zbuf == -1).all()), k
         assert torch.equal(so.view(torch.int32), v.dense_depth.view(torch.int32)), k
         assert torch.equal(sm, v.dense_valid), k
         _, d, b, _ = oracle.project(f.points[: len(pts)], f.camera.pose,
@@ -256,3 +272,80 @@ def test_batch_graph_replays_match_eager(tdev, frames):
                                e.dense_depth.view(torch.int32)), (rep, k)
             assert torch.equal(v.dense_valid, e.dense_valid), (rep, k)
         print(f"  replay {rep}: n={[v.n_points for v in views]} ok", flush=True)
+
+
+@pytest.mark.parametrize("prec_name", ["FP32", "FP16_RANGE"])
+def test_batch_one_launch_equals_staged(tdev, frames, prec_name):
+    """The one persistent launch (work queue over every view's clear,
+    projection, decode and filter items) and the staged launch sequence
+    give the same bits: keys, sparse depth and mask, dense depth and mask."""
+    torch, dev = tdev
+    from paper_2601_01210_amd import Precision, batch_check
+    prec = getattr(Precision, prec_name)
+    one = _views(torch, dev, frames)
+    staged = _views(torch, dev, frames)
+    t1, _ = _run(torch, one, prec)
+    t2, _ = _run(torch, staged, prec, staged=True)
+    batch_check(t1)
+    batch_check(t2)
+    for k, (a, b) in enumerate(zip(one, staged)):
+        _same_outputs(torch, a, b, (prec_name, k))
+
+
+def test_batch_one_launch_reruns_on_an_unchanged_table(tdev, frames):
+    """The last workgroup of a one-launch run resets the queue, so the same
+    table runs again without being rewritten and gives the same outputs."""
+    torch, dev = tdev
+    from paper_2601_01210_amd import Precision, batch_check, batch_run
+    views = _views(torch, dev, frames[:3])
+    table, _ = _run(torch, views, Precision.FP32)
+    first = [(v.dense_depth.clone(), v.dense_valid.clone(), v.zbuf.clone())
+             for v in views]
+    for v in views:                      # outputs are rewritten, not kept
+        v.dense_depth.fill_(7.0)
+        v.dense_valid.fill_(9)
+    for _ in range(2):
+        batch_run(table, 5, Precision.FP32)
+        torch.cuda.synchronize()
+        for (d, m, z), v in zip(first, views):
+            assert torch.equal(d.view(torch.int32), v.dense_depth.view(torch.int32))
+            assert torch.equal(m, v.dense_valid)
+            assert torch.equal(z, v.zbuf)
+    # the header's run words (workgroups exited, error) are zero again; the
+    # queues were reset too, or the reruns above would have done nothing
+    words = table[:48].cpu().numpy().view(np.uint32)
+    assert list(words[9:11]) == [0, 0]
+    batch_check(table)
+
+
+@pytest.mark.parametrize("staged", [False, True], ids=["one_launch", "staged"])
+def test_batch_radius_above_launch_bound_is_refused(tdev, staged):
+    """A view whose radius exceeds the run's max_radius (here r = 20 in a
+    run bounded by 16, whose LDS table holds windows up to r = 16) gets zero
+    depth and mask instead of a table overrun, the other views are
+    unaffected, and jbfd_batch_check reports JBFD_EINVAL; a run with an
+    adequate bound on a fresh table is clean."""
+    torch, dev = tdev
+    from paper_2601_01210_amd import Precision, batch_check, densify, project
+    from paper_2601_01210_amd.binding import JBFD_EINVAL, JbfdError
+    rng = np.random.default_rng(41)
+    f = S.small_view(rng, 320, 240)
+    g = S.small_view(rng, 160, 120, n_points=5000)
+    views = _views(torch, dev, [f, g])
+    views[0].radius, views[0].sigma_s = 20, 6.0
+    table, _ = _run(torch, views, Precision.FP32, staged=staged, max_radius=16)
+    assert int(views[0].dense_valid.sum()) == 0
+    assert int(views[0].dense_depth.abs().sum()) == 0
+    zs, ds, bs = project(views[1].points, views[1].pose, views[1].intrinsics,
+                         views[1].width, views[1].height)
+    so, sm = densify(ds, bs, views[1].rgb, views[1].radius, views[1].sigma_s,
+                     views[1].sigma_r, ws=None)
+    torch.cuda.synchronize()
+    assert torch.equal(so.view(torch.int32), views[1].dense_depth.view(torch.int32))
+    assert torch.equal(sm, views[1].dense_valid)
+    with pytest.raises(JbfdError) as e:
+        batch_check(table)
+    assert e.value.status == JBFD_EINVAL
+    ok_table, _ = _run(torch, views, Precision.FP32, staged=staged, max_radius=32)
+    batch_check(ok_table)
+    assert int(views[0].dense_valid.sum()) > 0
