@@ -354,14 +354,14 @@ size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
  * items from device queues in the table: every view's projection chunks,
  * then every view's key decode chunks, then every view's filter tiles, each
  * item waiting (bounded) only for the earlier items of its own view, so a
- * view is filtered while later views are still being decoded. It needs each
- * view's key buffer to hold only empty keys (UINT64_MAX) on entry: clear a
- * new buffer once with jbfd_zbuf_clear; every batch run, in either form,
+ * view is filtered while later views are still being decoded. With
+ * JBFD_BATCH_STAGED (or JBFD_BATCH_LISTS) the run is instead a sequence of
+ * fixed-grid launches (project, decode, with JBFD_BATCH_LISTS list count and
+ * list scatter, filter), each covering every view. Either form needs each
+ * view's key buffer to hold only empty keys (UINT64_MAX) on entry, and
  * leaves it so (the decode writes the empty key back over each key it
- * reads). With JBFD_BATCH_STAGED (or JBFD_BATCH_LISTS) the run is instead a
- * sequence of fixed-grid launches (clear, project, decode, with
- * JBFD_BATCH_LISTS list count and list scatter, filter), each covering
- * every view; it clears the keys itself. Either way every size is read from the table on the device,
+ * reads): clear a new buffer once with jbfd_zbuf_clear. Either way every
+ * size is read from the table on the device,
  * so the launch(es) can be captured once into a HIP graph and replayed for
  * any batch written into the same device table, as long as every radius
  * stays <= the captured max_radius; the one-launch run leaves its queue
@@ -385,8 +385,7 @@ typedef struct jbfd_view {
     int32_t radius;           /* 0 .. JBFD_MAX_RADIUS */
     float sigma_s, sigma_r;   /* as jbfd_densify */
     uint64_t *zbuf;           /* H*W key buffer (device): only empty keys
-                                 on entry of a one-launch run, and after
-                                 every run */
+                                 on entry, and again after every run */
     float *sparse_depth;      /* H*W scratch/output (device) */
     uint8_t *sparse_valid;    /* H*W scratch/output (device) */
     float *dense_depth;       /* H*W output (device) */

@@ -483,8 +483,8 @@ class BatchView:
         eight 720p/1080p views costs more than the walk saves at r = 5); at
         large radii the list walk is much cheaper than streaming.
 
-        A new key buffer is cleared to empty keys (jbfd_zbuf_clear), as the
-        one-launch batch run requires on entry; every batch run leaves it so."""
+        A new key buffer is cleared to empty keys (jbfd_zbuf_clear), as a
+        batch run requires on entry; every batch run leaves it so."""
         torch = _torch()
         dev = device if device is not None else self.points.device
         hw = (self.height, self.width)

@@ -146,27 +146,9 @@ __global__ __launch_bounds__(256) void k_decode(KeyPtr<RESET> keys, int64_t npix
 
 // Each workgroup takes chunks of kBatchChunk elements; chunk c belongs to
 // the view found by a scalar binary search of the chunk prefixes, so every
-// view's work is spread over the whole grid at once.
-
-__global__ __launch_bounds__(256) void k_batch_clear(const BatchHeader *__restrict__ hdr,
-                                                     const BatchView *__restrict__ views) {
-    const int n_views = hdr->n_views, chunks = hdr->px_chunks;
-    for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const BatchView &bv =
-            views[batch_view_of<&BatchView::px_chunk_off>(views, n_views, c)];
-        const int64_t npix = (int64_t)bv.W * bv.H;
-        const int64_t p0 = (int64_t)(c - bv.px_chunk_off) * kBatchChunk +
-                           4 * (int64_t)threadIdx.x;
-        uint64_t *keys = bv.zbuf;
-        if ((reinterpret_cast<uintptr_t>(keys) & 15) == 0 && p0 + 4 <= npix) {
-            const ulonglong2 e = make_ulonglong2(kEmptyKey, kEmptyKey);
-            *reinterpret_cast<ulonglong2 *>(keys + p0) = e;
-            *reinterpret_cast<ulonglong2 *>(keys + p0 + 2) = e;
-        } else {
-            for (int64_t p = p0; p < npix && p < p0 + 4; ++p) keys[p] = kEmptyKey;
-        }
-    }
-}
+// view's work is spread over the whole grid at once. The key buffers hold
+// only empty keys on entry and the decode writes the empty key back, so
+// there is no clearing pass.
 
 __global__ __launch_bounds__(256) void k_batch_project(const BatchHeader *__restrict__ hdr,
                                                        const BatchView *__restrict__ views) {
@@ -264,7 +246,6 @@ hipError_t launch_batch(void *d_table, int32_t max_radius, bool use_lists,
     const BatchView *views = reinterpret_cast<const BatchView *>(
         static_cast<const unsigned char *>(d_table) + sizeof(BatchHeader));
     const int grid = 2048;   // eight workgroups per CU, striding over chunks
-    k_batch_clear<<<grid, 256, 0, s>>>(hdr, views);
     k_batch_project<<<grid, 256, 0, s>>>(hdr, views);
     k_batch_decode<<<grid, 256, 0, s>>>(hdr, views);
     hipError_t e = hipGetLastError();
