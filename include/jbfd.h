@@ -86,7 +86,17 @@ extern "C" {
  * in which the FP32 kernels keep it exact. */
 #define JBFD_MIN_SIGMA 0.25f
 
-typedef enum jbfd_status {
+/* Enumerations cross the ABI as 32-bit ints. A caller may pass any int where
+ * one is expected (an unknown value is rejected as JBFD_EINVAL, or named
+ * "unknown status"); C++ gives the enumerations int as their underlying type
+ * so that every int is a value of the type there as well. */
+#ifdef __cplusplus
+#define JBFD_ENUM_INT : int
+#else
+#define JBFD_ENUM_INT
+#endif
+
+typedef enum jbfd_status JBFD_ENUM_INT {
     JBFD_OK = 0,
     JBFD_EINVAL = 1,      /* bad argument (null pointer, size, radius, sigma) */
     JBFD_EUNSUPPORTED = 2, /* valid request this library does not implement */
@@ -94,7 +104,7 @@ typedef enum jbfd_status {
     JBFD_ENOSPC = 4       /* caller workspace smaller than the queried size */
 } jbfd_status;
 
-typedef enum jbfd_precision {
+typedef enum jbfd_precision JBFD_ENUM_INT {
     JBFD_FP32 = 0,        /* weights, sums and divide in FP32 */
     JBFD_FP16_RANGE = 1   /* colour differences and range weights in FP16,
                              spatial weight, depth, sums, divide in FP32 */
@@ -337,7 +347,8 @@ jbfd_status jbfd_densify_backward(const float *sparse_depth,
                                   double *grad_sigmas, void *ws,
                                   size_t ws_bytes, void *stream);
 
-/* Workspace bytes needed by jbfd_densify_backward for an H x W image. */
+/* Workspace bytes needed by jbfd_densify_backward for an H x W image; 0
+ * when H or W is outside 1 .. JBFD_MAX_SIDE (such a call is rejected). */
 size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
 
 /*

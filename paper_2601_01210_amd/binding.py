@@ -16,7 +16,9 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libjbfd.so")
+# JBFD_LIB names another build of the library (e.g. one whose host code is
+# compiled with sanitizers); by default the in-tree libjbfd.so
+_LIB_PATH = os.environ.get("JBFD_LIB") or os.path.join(_HERE, "libjbfd.so")
 
 JBFD_OK, JBFD_EINVAL, JBFD_EUNSUPPORTED, JBFD_EHIP, JBFD_ENOSPC = range(5)
 

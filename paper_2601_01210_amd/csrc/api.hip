@@ -395,7 +395,7 @@ size_t jbfd_densify_ws_bytes(int32_t H, int32_t W, int32_t radius,
 }
 
 size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W) {
-    if (H <= 0 || W <= 0) return 0;
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE) return 0;
     return jbfd::backward_ws_bytes(H, W);
 }
 

@@ -168,6 +168,10 @@ def test_backward_workspace_checks(L):
     need = L.jbfd_densify_backward_ws_bytes(100, 100)
     assert need > 0
     assert L.jbfd_densify_backward_ws_bytes(0, 100) == 0
+    # the same side limit as every other workspace query
+    assert L.jbfd_densify_backward_ws_bytes(32768, 100) == 0
+    assert L.jbfd_densify_backward_ws_bytes(100, 32768) == 0
+    assert L.jbfd_densify_backward_ws_bytes(32767, 1) > 0
     st = L.jbfd_densify_backward(f, f, f, 100, 100, 3, C.c_float(2),
                                  C.c_float(10), f, f, f, f, f, f, need - 1,
                                  None)
