@@ -491,25 +491,232 @@ __global__ __launch_bounds__(256) void k_list_scatter(
 // ---------------------------------------------------------------------------
 
 // Scratch of one filter workgroup (LDS).
+// Workgroup-level staging of a tile's halo (STAGE): the valid samples of
+// the tile plus r pixels on every side are gathered once for the four
+// waves (each wave streaming its own block's halo reads most pixels two to
+// four times), then each wave copies the ones in its block's halo into its
+// list. Capacities: samples of the tile's halo, samples of one block's.
+constexpr int kTileCap = 256;
+constexpr int kSubCap = 128;
+
+// rounds of 256 pixels that cover a tile's halo at radius r <= RMAX
 template <int RMAX>
-struct FilterShared {
+constexpr int stage_rounds() {
+    return ((kTile + 2 * RMAX) * (kTile + 2 * RMAX) + 255) / 256;
+}
+
+template <int RMAX, bool STAGE>
+struct FilterShared;
+
+template <int RMAX>
+struct FilterShared<RMAX, false> {
     float G[(2 * RMAX + 15) * table_stride(RMAX)];
     Rec recs[kWaves][64];
     float nq2h[kWaves][64];
 };
 
+template <int RMAX>
+struct FilterShared<RMAX, true> {
+    float G[(2 * RMAX + 15) * table_stride(RMAX)];
+    Rec recs[kWaves][kSubCap];    // each wave's list (or its stream chunks)
+    float nq2h[kWaves][kSubCap];
+    Rec trec[kTileCap];           // the tile halo's samples, xy = x | y << 16
+    float tq[kTileCap];
+    int tcnt[stage_rounds<RMAX>() * kWaves];   // samples per (round, wave)
+};
+
+// Stage the valid samples of tile (tx, ty)'s halo (clipped to the image):
+// every thread of the workgroup calls it. Pixel k of the halo in row-major
+// order is handled in round k / 256 by thread k mod 256, so ordering the
+// samples by (round, wave, lane) keeps row-major order. Returns the number
+// of samples of block (bx, by)'s halo now in the wave's list (row-major,
+// records as the stream writes them), or -1 when a capacity is exceeded
+// (the wave then streams its halo itself).
+template <int RMAX>
+__device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict__ B,
+                          const uint8_t *__restrict__ rgb, int H, int W, int r,
+                          int tx, int ty, int bx, int by, FilterShared<RMAX, true> &sh) {
+    constexpr int kMaxRounds = stage_rounds<RMAX>();
+    static_assert(kMaxRounds * kWaves <= 128 && kMaxRounds + 3 <= 32,
+                  "each wave scans the round counts, two per lane");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int X0 = max(tx * kTile - r, 0), X1 = min(tx * kTile + kTile + r, W);
+    const int Y0 = max(ty * kTile - r, 0), Y1 = min(ty * kTile + kTile + r, H);
+    const int rw = X1 - X0;                 // >= 1: the tile holds a pixel
+    const int n = rw * (Y1 - Y0);
+    const int rounds = (n + 255) >> 8;      // <= kMaxRounds
+    // round 0: pixel tid of the halo, at (tid mod rw, tid div rw); (tid +
+    // 0.5) / rw lies at least 0.5 / rw from an integer, far above the
+    // product's rounding error
+    const int cy0 = (int)(((float)tid + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
+    const int cx0 = tid - cy0 * rw;
+    const uint32_t Wu = (uint32_t)W;
+    const uint32_t first = (uint32_t)Y0 * Wu + (uint32_t)X0;
+    const uint32_t p0 = first + (uint32_t)cy0 * Wu + (uint32_t)cx0;
+    const uint32_t xy0 = (uint32_t)(X0 + cx0) | ((uint32_t)(Y0 + cy0) << 16);
+    // per round: 256 pixels further
+    const int sx = 256 % rw, sy = 256 / rw;
+    const uint32_t dp = (uint32_t)sy * Wu + (uint32_t)sx, dp_wrap = Wu - (uint32_t)rw;
+    const uint32_t dxy = (uint32_t)sx + ((uint32_t)sy << 16);
+    const uint32_t dxy_wrap = (1u << 16) - (uint32_t)rw;   // x - rw, y + 1
+    __syncthreads();   // the previous tile's waves have read trec and tcnt
+
+    // (A) validity of each round's pixel, counted per (round, wave); four
+    // rounds' mask bytes are loaded together. (Loading the first rounds'
+    // sample data here already, to land under the count exchange, measured
+    // 7% slower on the eight-view batch: the registers it holds cost the
+    // kernel occupancy.)
+    uint32_t vbits = 0;
+    auto load_sample = [&](uint32_t q, uint32_t &ac, float &ad) {
+        const uint32_t o3 = q * 3u;
+        ac = (uint32_t)rgb[o3] | ((uint32_t)rgb[o3 + 1u] << 8) |
+             ((uint32_t)rgb[o3 + 2u] << 16);
+        ad = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(D) +
+                                              (q << 2));
+    };
+    {
+        int cx = cx0;
+        uint32_t p = p0;
+        for (int j0 = 0; j0 < rounds; j0 += 4) {
+            uint32_t q[4];
+            bool in[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                in[u] = (j0 + u) * 256 + tid < n;
+                q[u] = in[u] ? p : first;
+                cx += sx;
+                p += dp;
+                if (cx >= rw) {
+                    cx -= rw;
+                    p += dp_wrap;
+                }
+            }
+            uint32_t m[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) m[u] = B[q[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool v = in[u] && m[u] != 0u;
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(v);
+                if (lane == 0 && j0 + u < rounds)
+                    sh.tcnt[(j0 + u) * kWaves + wid] = __builtin_popcountll(bal);
+                vbits |= (uint32_t)v << (j0 + u);
+            }
+        }
+    }
+    __syncthreads();
+    // every wave scans the counts in (round, wave) order itself (exclusive
+    // prefix: entry e in lane e, entry 64 + e in lane e of the second half)
+    const int ne = rounds * kWaves;
+    const int ca = lane < ne ? sh.tcnt[lane] : 0;
+    const int cb = lane + 64 < ne ? sh.tcnt[lane + 64] : 0;
+    const int ia = wave_inclusive_scan(ca);
+    const int ib = wave_inclusive_scan(cb) + __builtin_amdgcn_readlane(ia, 63);
+    const int xa = ia - ca, xb = ib - cb;
+    const int total = __builtin_amdgcn_readlane(ib, 63);
+    if (total > kTileCap) return -1;   // the same in every wave
+    auto base_of = [&](int j) -> int {   // wave-uniform j
+        const int e = j * kWaves + wid;
+        return e < 64 ? __builtin_amdgcn_readlane(xa, e)
+                      : __builtin_amdgcn_readlane(xb, e - 64);
+    };
+
+    // (B) records of the valid pixels at their ranks, the sample data of
+    // four rounds loaded together
+    {
+        int cx = cx0;
+        uint32_t p = p0, xy = xy0;
+        for (int j0 = 0; j0 < rounds; j0 += 4) {
+            uint32_t q[4], qxy[4];
+            bool v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = (vbits >> (j0 + u)) & 1u;
+                q[u] = p;
+                qxy[u] = xy;
+                cx += sx;
+                p += dp;
+                xy += dxy;
+                if (cx >= rw) {
+                    cx -= rw;
+                    p += dp_wrap;
+                    xy += dxy_wrap;
+                }
+            }
+            uint32_t cc[4];   // colour bytes r | g << 8 | b << 16
+            float dd[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cc[u] = 0u;
+                dd[u] = 0.0f;
+                if (v[u]) load_sample(q[u], cc[u], dd[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(v[u]);
+                if (j0 + u < rounds && bal != 0u) {   // uniform
+                    const int b0 = base_of(j0 + u);
+                    if (v[u]) {
+                        const int pos = b0 + (int)__builtin_amdgcn_mbcnt_hi(
+                                                 (uint32_t)(bal >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        Rec rec;
+                        float q2h;
+                        colour_fields(cc[u] & 0xffffu, cc[u] >> 16, rec.rg, rec.b0, q2h);
+                        rec.xy = qxy[u];
+                        rec.d = dd[u];
+                        sh.trec[pos] = rec;
+                        sh.tq[pos] = q2h;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // (C) this wave's block halo, in order, into its list (a block outside
+    // the image has nothing to filter)
+    if (bx >= W || by >= H) return 0;
+    const int hx0 = max(bx - r, 0), hx1 = min(bx + 8 + r, W);
+    const int hy0 = max(by - r, 0), hy1 = min(by + 8 + r, H);
+    const uint32_t xoff = (uint32_t)(bx - r);   // record x is x - (bx - r)
+    Rec *my = sh.recs[wid];
+    float *myq = sh.nq2h[wid];
+    int cnt = 0;
+    for (int k0 = 0; k0 < total; k0 += 64) {
+        const int k = k0 + lane;
+        const int kk = k < total ? k : 0;
+        Rec rec = sh.trec[kk];
+        const float q2h = sh.tq[kk];
+        const int x = (int)(rec.xy & 0xffffu), y = (int)(rec.xy >> 16);
+        const bool mine = k < total && x >= hx0 && x < hx1 && y >= hy0 && y < hy1;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(mine);
+        const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                  (uint32_t)(bal >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (mine && pos < kSubCap) {
+            rec.xy -= xoff;
+            my[pos] = rec;
+            myq[pos] = q2h;
+        }
+        cnt += __builtin_popcountll(bal);
+    }
+    return cnt <= kSubCap ? cnt : -1;
+}
+
 // Filter one 16x16 output tile (tx, ty) of an image with one 256-thread
 // workgroup: builds the spatial table, then each wave filters its 8x8 block.
 // Every thread returns normally, so callers may loop over tiles with a
 // barrier between them.
-template <int RMAX, int PREC>
+template <int RMAX, int PREC, bool STAGE>
 __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
                             const uint8_t *__restrict__ B,
                             const uint8_t *__restrict__ rgb, int H, int W,
                             const FilterParams &fp, const ListArgs &la, int tx,
                             int ty, float *__restrict__ out,
                             uint8_t *__restrict__ mask, float2 *__restrict__ aux,
-                            FilterShared<RMAX> &sh, bool build = true) {
+                            FilterShared<RMAX, STAGE> &sh, bool build = true) {
     const int r = fp.radius;
     const int ts = table_stride(r);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -530,6 +737,13 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
         build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
         __syncthreads();
     }
+    // without sample lists the workgroup stages the tile's halo once
+    // (every thread takes part, before any block leaves)
+    int staged = -1;
+    if constexpr (STAGE) {
+        if (la.recs == nullptr)   // uniform
+            staged = tile_stage<RMAX>(D, B, rgb, H, W, r, tx, ty, bx, by, sh);
+    }
     if (bx >= W || by >= H) return;  // block of a partial tile: no outputs
 
     uint32_t prg, pb0;
@@ -547,7 +761,7 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     const BlockWalker bw{D, B, rgb, H, W, r, la, bx, by, lane, prg, pb0, lxy,
                          gstride, lc, ts,
                          reinterpret_cast<const unsigned char *>(sh.G),
-                         sh.recs[wid], sh.nq2h[wid], -fp.ks};
+                         sh.recs[wid], sh.nq2h[wid], -fp.ks, staged};
 
     // Pass 1: fixed per-lane shift. Every exponent E = -kr c - ks s is <= 0,
     // so a = fma(2kr, t, -kr|p|^2) + G (the fma rounds once, relative to the
@@ -656,17 +870,17 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     }
 }
 
-template <int RMAX, int PREC>
+template <int RMAX, int PREC, bool STAGE>
 __global__ __launch_bounds__(256) void k_jbf_fwd(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
     int tiles_x, int tiles_y, ListArgs la, float *__restrict__ out,
     uint8_t *__restrict__ mask, float2 *__restrict__ aux) {
-    __shared__ FilterShared<RMAX> sh;
+    __shared__ FilterShared<RMAX, STAGE> sh;
     int tx, ty;
     if (!column_tile(blockIdx.x, tiles_x, tiles_y, tx, ty))
         return;  // whole workgroup leaves together
-    filter_tile<RMAX, PREC>(D, B, rgb, H, W, fp, la, tx, ty, out, mask, aux, sh);
+    filter_tile<RMAX, PREC, STAGE>(D, B, rgb, H, W, fp, la, tx, ty, out, mask, aux, sh);
 }
 
 hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
@@ -706,21 +920,30 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
         la = ListArgs{v.recs, v.rowoff, v.capacity};
     }
     float2 *a2 = reinterpret_cast<float2 *>(aux);
-    const bool small = fp.radius <= 16;
+    // with sample lists no staging (its LDS would cost the list walk
+    // occupancy); without, the workgroup stages each tile's halo
+    auto go = [&](auto rmax, auto prc, auto stage, float2 *ax) {
+        k_jbf_fwd<decltype(rmax)::value, decltype(prc)::value, decltype(stage)::value>
+            <<<n_wg, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out,
+                                  mask, ax);
+    };
+    using F32 = std::integral_constant<int, JBFD_FP32>;
+    using F16 = std::integral_constant<int, JBFD_FP16_RANGE>;
+    using R16 = std::integral_constant<int, 16>;
+    using R32 = std::integral_constant<int, JBFD_MAX_RADIUS>;
+    using Yes = std::true_type;
+    using No = std::false_type;
+    const bool small = fp.radius <= 16, lists = la.recs != nullptr;
     if (prec == JBFD_FP32) {
         if (small)
-            k_jbf_fwd<16, JBFD_FP32><<<n_wg, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, a2);
+            lists ? go(R16{}, F32{}, No{}, a2) : go(R16{}, F32{}, Yes{}, a2);
         else
-            k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP32><<<n_wg, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, a2);
+            lists ? go(R32{}, F32{}, No{}, a2) : go(R32{}, F32{}, Yes{}, a2);
     } else {
         if (small)
-            k_jbf_fwd<16, JBFD_FP16_RANGE><<<n_wg, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, nullptr);
+            lists ? go(R16{}, F16{}, No{}, nullptr) : go(R16{}, F16{}, Yes{}, nullptr);
         else
-            k_jbf_fwd<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<n_wg, 256, 0, s>>>(
-                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, nullptr);
+            lists ? go(R32{}, F16{}, No{}, nullptr) : go(R32{}, F16{}, Yes{}, nullptr);
     }
     return hipGetLastError();
 }
@@ -775,20 +998,28 @@ __device__ inline void refuse_tile(BatchHeader *hdr, const BatchView &v, int tx,
 // Filter tiles of every view of a batch: a fixed grid walks the flattened
 // tile space (views back to back); each workgroup finds its view by a
 // binary search of the table's tile offsets (wave-uniform scalar loads).
-template <int RMAX, int PREC>
+template <int RMAX, int PREC, bool STAGE>
 __global__ __launch_bounds__(256) void k_batch_filter(BatchHeader *__restrict__ hdr,
                                                       const BatchView *__restrict__ views,
                                                       bool use_lists) {
-    __shared__ FilterShared<RMAX> sh;
+    __shared__ FilterShared<RMAX, STAGE> sh;
     const int n_views = hdr->n_views;
     const int total = hdr->total_tiles;
     // the spatial table depends on the radius and sigma_s only: it is
     // rebuilt when a tile's view differs in either from the previous tile's
     int cur_r = -1;
     float cur_ks = 0.0f;
+    // t only grows, so the view is looked up again only when t passes the
+    // next view's first tile (a binary search per tile, a chain of
+    // dependent scalar loads, cost the batch 35 us of waiting)
+    int next_off = -1;
+    BatchView v;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int lo = batch_view_of<&BatchView::tile_off>(views, n_views, t);
-        const BatchView &v = views[lo];
+        if (t >= next_off) {   // uniform
+            const int lo = batch_view_of<&BatchView::tile_off>(views, n_views, t);
+            v = global_view(views[lo]);
+            next_off = lo + 1 < n_views ? views[lo + 1].tile_off : total;
+        }
         const int local = t - v.tile_off;
         const int ty = local / v.tiles_x, tx = local - ty * v.tiles_x;
         if (v.radius > RMAX) {   // uniform: the table would not fit
@@ -800,8 +1031,8 @@ __global__ __launch_bounds__(256) void k_batch_filter(BatchHeader *__restrict__ 
         if (rebuild && cur_r >= 0) __syncthreads();  // old table no longer read
         // lists only when this run built them (recs null: stream)
         const ListArgs la{use_lists ? v.recs : nullptr, v.rowoff, v.capacity};
-        filter_tile<RMAX, PREC>(v.sd, v.sv, v.rgb, v.H, v.W, fp, la, tx, ty,
-                                v.out, v.mask, nullptr, sh, rebuild);
+        filter_tile<RMAX, PREC, STAGE>(v.sd, v.sv, v.rgb, v.H, v.W, fp, la, tx, ty,
+                                       v.out, v.mask, nullptr, sh, rebuild);
         cur_r = fp.radius;
         cur_ks = fp.ks;
     }
@@ -815,7 +1046,8 @@ __global__ __launch_bounds__(256) void k_batch_list_count(const BatchHeader *__r
                                                           const BatchView *__restrict__ views) {
     const int n_views = hdr->n_views, units = hdr->list_units;
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
-        const BatchView &v = views[batch_view_of<&BatchView::unit_off>(views, n_views, u)];
+        const BatchView v =
+            global_view(views[batch_view_of<&BatchView::unit_off>(views, n_views, u)]);
         const int local = u - v.unit_off;
         const int band = local / v.n_groups, g = local - band * v.n_groups;
         list_count_unit(v.sv, v.H, v.W, v.radius, v.n_strips, v.n_bands, v.bandcnt,
@@ -828,7 +1060,8 @@ __global__ __launch_bounds__(256) void k_batch_list_scatter(const BatchHeader *_
                                                             const BatchView *__restrict__ views) {
     const int n_views = hdr->n_views, units = hdr->list_units;
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
-        const BatchView &v = views[batch_view_of<&BatchView::unit_off>(views, n_views, u)];
+        const BatchView v =
+            global_view(views[batch_view_of<&BatchView::unit_off>(views, n_views, u)]);
         const int local = u - v.unit_off;
         const int band = local / v.n_groups, g = local - band * v.n_groups;
         list_scatter_unit(v.sd, v.sv, v.rgb, v.H, v.W, v.radius, v.n_strips,
@@ -849,18 +1082,23 @@ hipError_t launch_batch_lists(const BatchHeader *hdr, const BatchView *views,
 hipError_t launch_batch_filter(BatchHeader *hdr, const BatchView *views,
                                int32_t max_radius, jbfd_precision prec,
                                bool use_lists, hipStream_t s) {
-    const int grid = 2048;   // 8 workgroups per CU
+    // views with sample lists (JBFD_BATCH_LISTS) walk them; the others
+    // stage each tile's halo, which leaves LDS for 6 workgroups per CU at
+    // RMAX = 16 (a view streams the same way with or without the flag)
+    const int grid = 1536;
     if (max_radius <= 16) {
         if (prec == JBFD_FP32)
-            k_batch_filter<16, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views, use_lists);
+            k_batch_filter<16, JBFD_FP32, true><<<grid, 256, 0, s>>>(hdr, views, use_lists);
         else
-            k_batch_filter<16, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr, views, use_lists);
+            k_batch_filter<16, JBFD_FP16_RANGE, true><<<grid, 256, 0, s>>>(hdr, views,
+                                                                           use_lists);
     } else {
         if (prec == JBFD_FP32)
-            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP32><<<grid, 256, 0, s>>>(hdr, views, use_lists);
+            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP32, true><<<grid, 256, 0, s>>>(
+                hdr, views, use_lists);
         else
-            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP16_RANGE><<<grid, 256, 0, s>>>(hdr,
-                                                                                views, use_lists);
+            k_batch_filter<JBFD_MAX_RADIUS, JBFD_FP16_RANGE, true><<<grid, 256, 0, s>>>(
+                hdr, views, use_lists);
     }
     return hipGetLastError();
 }
@@ -1047,11 +1285,12 @@ __device__ inline int queue_item(int q, uint32_t k) {
 // Six waves per SIMD at RMAX = 16: 80 registers, none spilled (at eight, as
 // the staged filter kernel has, 14 registers of loop state go to scratch
 // and the eight-view batch took 0.275 ms; at seven, 2 and 0.258 ms; at six
-// 0.253 ms). The LDS of the RMAX = 32 table allows four.
+// 0.253 ms); the LDS of the halo staging also leaves room for six
+// workgroups per CU. At RMAX = 32 the LDS allows three.
 template <int RMAX, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RMAX <= 16 ? 6 : 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RMAX <= 16 ? 6 : 3)))
 void k_batch_fused(BatchHeader *__restrict__ hdr, const BatchView *__restrict__ views) {
-    __shared__ FilterShared<RMAX> sh;
+    __shared__ FilterShared<RMAX, true> sh;
     __shared__ int s_item, s_ok;
     const int n_views = hdr->n_views;
     unsigned char *state =
@@ -1072,19 +1311,19 @@ void k_batch_fused(BatchHeader *__restrict__ hdr, const BatchView *__restrict__ 
         if (threadIdx.x == 0) next = queue_item(q, atomicAdd(turn, 1u));
         if (item < P) {
             const int v = batch_view_of<&BatchView::fpt_off>(views, n_views, item);
-            project_chunk(views[v], item - views[v].fpt_off);
+            project_chunk(global_view(views[v]), item - views[v].fpt_off);
             publish(&cnt[v].projected.n);
         } else if (item < P + C) {
             const int c = item - P;
             const int v = batch_view_of<&BatchView::fpx_off>(views, n_views, c);
-            const BatchView &bv = views[v];
+            const BatchView bv = global_view(views[v]);
             await_count(&cnt[v].projected.n, point_items(bv), hdr, s_ok);
             decode_chunk(bv, c - bv.fpx_off);
             publish(&cnt[v].decoded.n);
         } else {
             const int t = item - P - C;
             const int v = batch_view_of<&BatchView::ftile_off>(views, n_views, t);
-            const BatchView &bv = views[v];
+            const BatchView bv = global_view(views[v]);
             const int t0 = kFusedTiles * (t - bv.ftile_off);
             if (bv.radius > RMAX) {   // uniform: the table would not fit
                 for (int lt = t0; lt < min(t0 + kFusedTiles, bv.n_tiles); ++lt)
@@ -1097,7 +1336,7 @@ void k_batch_fused(BatchHeader *__restrict__ hdr, const BatchView *__restrict__ 
                 bool rebuild = fp.radius != cur_r || fp.ks != cur_ks;
                 const ListArgs none{nullptr, nullptr, 0};
                 for (int lt = t0; lt < min(t0 + kFusedTiles, bv.n_tiles); ++lt) {
-                    filter_tile<RMAX, PREC>(bv.sd, bv.sv, bv.rgb, bv.H, bv.W, fp, none,
+                    filter_tile<RMAX, PREC, true>(bv.sd, bv.sv, bv.rgb, bv.H, bv.W, fp, none,
                                             lt % bv.tiles_x, lt / bv.tiles_x, bv.out,
                                             bv.mask, nullptr, sh, rebuild);
                     rebuild = false;

@@ -298,6 +298,8 @@ struct BlockWalker {
     Rec *my;               // the wave's LDS list
     float *myq;
     float nks;             // -ks
+    int staged = -1;       // samples of the block's halo that the workgroup
+                           // staged into `my` (row-major), or -1: stream
 
     // exact spatial exponent: -ks (dx^2+dy^2) inside the window, -inf outside
     __device__ float exact_g(uint32_t u) const {
@@ -484,6 +486,10 @@ struct BlockWalker {
             walk_list<EXACT>(lo, hi, eat4, eat1);
             return;
         }
+        if (staged >= 0) {
+            run_chunk<EXACT>(staged, eat4, eat1);
+            return;
+        }
         stream<EXACT>(eat4, eat1);
     }
 
@@ -500,6 +506,10 @@ struct BlockWalker {
                 walk_list<true>(lo, hi, eat4, eat1);
             return;
         }
+        if (staged >= 0) {
+            run_chunk<true>(staged, eat4, eat1);
+            return;
+        }
         stream<true>(eat4, eat1);
     }
 
@@ -512,10 +522,20 @@ struct BlockWalker {
             walk_list_split(lo, hi, stage_a, stage_b, eat1, g_none);
             return;
         }
+        if (staged >= 0) {
+            run_chunk<false>(staged, eat4, eat1);
+            return;
+        }
         stream<false>(eat4, eat1);
     }
 
     // ---- stream the block's halo from the images ----
+    // The halo is walked in row-major order, 64 pixels per chunk, lane k of
+    // a chunk at halo position (64 c + k) mod hw, div hw. Each lane steps
+    // its pixel offset, column and record position by the chunk's constant
+    // strides (plus a row wrap), and addresses the images with 32-bit
+    // offsets from their bases (every offset of an image of at most
+    // JBFD_MAX_SIDE^2 pixels, times 4, fits in 32 bits).
     template <bool EXACT, class E4, class E1>
     __device__ void stream(E4 &eat4, E1 &eat1) const {
         const int hx0 = max(bx - r, 0), hx1 = min(bx + 8 + r, W);
@@ -523,32 +543,45 @@ struct BlockWalker {
         const int hw = hx1 - hx0;          // >= 1: the block holds a pixel
         const int npx = hw * (hy1 - hy0);
         const int step_x = 64 % hw, step_y = 64 / hw;
-        int cx = lane % hw, cy = lane / hw;          // this lane's pixel, chunk 0
+        // (lane + 0.5) / hw lies at least 0.5 / hw from an integer, far
+        // above the product's rounding error, so the floor is lane div hw
+        const int cy0 = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)hw));
+        int cx = lane - cy0 * hw;
+        const uint32_t Wu = (uint32_t)W;
+        const uint32_t first = (uint32_t)hy0 * Wu + (uint32_t)hx0;
+        uint32_t p = first + (uint32_t)cy0 * Wu + (uint32_t)cx;
+        uint32_t xy = (uint32_t)(hx0 + cx - (bx - r)) | ((uint32_t)(hy0 + cy0) << 16);
+        const uint32_t dp = (uint32_t)step_y * Wu + (uint32_t)step_x;
+        const uint32_t dp_wrap = Wu - (uint32_t)hw;
+        const uint32_t dxy = (uint32_t)step_x + ((uint32_t)step_y << 16);
+        const uint32_t dxy_wrap = (1u << 16) - (uint32_t)hw;   // x - hw, y + 1
         auto advance = [&]() {
             cx += step_x;
-            cy += step_y;
+            p += dp;
+            xy += dxy;
             if (cx >= hw) {
                 cx -= hw;
-                cy += 1;
+                p += dp_wrap;
+                xy += dxy_wrap;
             }
         };
-        // pixel index of this lane in the current chunk (clamped to the first
-        // halo pixel past the end, so the mask load is always in bounds)
-        auto pix = [&](int base) -> uint32_t {
-            const bool in = base + lane < npx;
-            return in ? (uint32_t)(hy0 + cy) * (uint32_t)W + (uint32_t)(hx0 + cx)
-                      : (uint32_t)hy0 * (uint32_t)W + (uint32_t)hx0;
+        // the lane's pixel offset in the chunk starting at halo index base,
+        // or the first halo pixel past the end (an in-bounds mask load)
+        auto pix = [&](int base) -> uint32_t { return base + lane < npx ? p : first; };
+        const char *Dc = reinterpret_cast<const char *>(D);
+        auto load_sample = [&](uint32_t q, uint32_t &c01, uint32_t &c2, float &d) {
+            const uint32_t o3 = q * 3u;
+            c01 = (uint32_t)rgb[o3] | ((uint32_t)rgb[o3 + 1u] << 8);
+            c2 = rgb[o3 + 2u];
+            d = *reinterpret_cast<const float *>(Dc + (q << 2));
         };
-        auto xy_of = [&]() -> uint32_t {
-            return (uint32_t)(hx0 + cx - (bx - r)) | ((uint32_t)(hy0 + cy) << 16);
-        };
-        auto stage = [&](bool v, uint64_t bal, uint32_t xy, uint32_t c01,
+        auto stage = [&](bool v, uint64_t bal, uint32_t xyv, uint32_t c01,
                          uint32_t c2, float d) {
             if (v) {
                 Rec rec;
                 float q2h;
                 colour_fields(c01, c2, rec.rg, rec.b0, q2h);
-                rec.xy = xy;
+                rec.xy = xyv;
                 rec.d = d;
                 const int pos = __builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
@@ -560,19 +593,14 @@ struct BlockWalker {
         // and the sample data of chunk c+1 load while chunk c is processed;
         // loaded values are consumed only after the compute loop
         __builtin_amdgcn_wave_barrier();
-        uint32_t p0 = pix(0);
-        bool v0 = (B[p0] != 0) && (lane < npx);
-        uint64_t bal0 = __builtin_amdgcn_ballot_w64(v0);
+        const uint32_t p0 = pix(0);
+        const bool v0 = (B[p0] != 0) && (lane < npx);
+        const uint64_t bal0 = __builtin_amdgcn_ballot_w64(v0);
         {
             uint32_t c01 = 0, c2 = 0;
             float d = 0.0f;
-            if (v0) {
-                const uint8_t *c = rgb + 3 * (int64_t)p0;
-                c01 = (uint32_t)c[0] | ((uint32_t)c[1] << 8);
-                c2 = c[2];
-                d = D[p0];
-            }
-            stage(v0, bal0, xy_of(), c01, c2, d);
+            if (v0) load_sample(p0, c01, c2, d);
+            stage(v0, bal0, xy, c01, c2, d);
         }
         advance();
         uint32_t p1 = pix(64);
@@ -581,15 +609,10 @@ struct BlockWalker {
         for (int base = 0; base < npx; base += 64) {
             const bool v1 = (m1 != 0u) && (base + 64 + lane < npx);
             const uint64_t bal1 = __builtin_amdgcn_ballot_w64(v1);
-            const uint32_t xy1 = xy_of();
+            const uint32_t xy1 = xy;
             uint32_t c01 = 0, c2 = 0;
             float d1 = 0.0f;
-            if (v1) {
-                const uint8_t *c = rgb + 3 * (int64_t)p1;
-                c01 = (uint32_t)c[0] | ((uint32_t)c[1] << 8);
-                c2 = c[2];
-                d1 = D[p1];
-            }
+            if (v1) load_sample(p1, c01, c2, d1);
             advance();
             const uint32_t p2n = pix(base + 128);
             const uint32_t m2 = B[p2n];

@@ -103,7 +103,14 @@ struct BatchView {
     int32_t fpt_off;
     int32_t ftile_off;
     int32_t pad_;
+    // launch-sequence filter: XCD c takes the tile columns tx = c (mod
+    // kXcds) of every view; band_off[c] is the exclusive prefix over the
+    // views of their tiles in those columns
+    int32_t band_off[8];
 };
+
+// XCDs of the chip: workgroup w of a launch runs on XCD w mod kXcds
+constexpr int kXcds = 8;
 
 // Elements (pixels or points) one workgroup handles per chunk of the
 // launch-sequence batch.
@@ -133,6 +140,8 @@ struct BatchHeader {
     uint32_t exited;        // workgroups that have finished
     uint32_t error;         // kBatchErr* bits of the runs since preparation
     uint32_t pad_;
+    int32_t band_tiles[8];  // tiles in the columns of XCD c over all views
+    uint32_t pad2_[2];
 };
 
 // error bits of a batch run
@@ -160,6 +169,34 @@ inline size_t batch_queues_offset(int32_t n_views) {
 
 inline size_t batch_counters_offset(int32_t n_views) {
     return batch_queues_offset(n_views) + kQueues * sizeof(BatchLine);
+}
+
+// A pointer the kernel read from memory (a view of the descriptor table) is
+// generic to the compiler, which then accesses it with flat instructions.
+// Flat loads count on the LDS counter as well, so every wait for an LDS
+// read would also wait for them. Routing the pointer through an integer
+// into the global address space makes its accesses global ones; every
+// pointer a caller hands in is device global memory.
+template <class T>
+__device__ __forceinline__ T *as_global(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
+// A copy of a view whose pointers are marked global (as_global).
+__device__ inline BatchView global_view(const BatchView &v) {
+    BatchView g = v;
+    g.pts = as_global(v.pts);
+    g.rgb = as_global(v.rgb);
+    g.zbuf = as_global(v.zbuf);
+    g.sd = as_global(v.sd);
+    g.sv = as_global(v.sv);
+    g.out = as_global(v.out);
+    g.mask = as_global(v.mask);
+    g.recs = as_global(v.recs);
+    g.rowoff = as_global(v.rowoff);
+    g.bandcnt = as_global(v.bandcnt);
+    g.grpcnt = as_global(v.grpcnt);
+    return g;
 }
 
 // Last view v with views[v].*field <= c (the fields are exclusive prefixes,

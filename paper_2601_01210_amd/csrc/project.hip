@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256) void k_batch_project(const BatchHeader *__rest
                                                        const BatchView *__restrict__ views) {
     const int n_views = hdr->n_views, chunks = hdr->pt_chunks;
     for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const BatchView &bv =
-            views[batch_view_of<&BatchView::pt_chunk_off>(views, n_views, c)];
+        const BatchView bv =
+            global_view(views[batch_view_of<&BatchView::pt_chunk_off>(views, n_views, c)]);
         unsigned long long *keys = reinterpret_cast<unsigned long long *>(bv.zbuf);
         const int64_t i0 = (int64_t)(c - bv.pt_chunk_off) * kBatchChunk + threadIdx.x;
         // four points per thread, 256 apart (coalesced); every point's
@@ -177,8 +177,8 @@ __global__ __launch_bounds__(256) void k_batch_decode(const BatchHeader *__restr
                                                       const BatchView *__restrict__ views) {
     const int n_views = hdr->n_views, chunks = hdr->px_chunks;
     for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const BatchView &bv =
-            views[batch_view_of<&BatchView::px_chunk_off>(views, n_views, c)];
+        const BatchView bv =
+            global_view(views[batch_view_of<&BatchView::px_chunk_off>(views, n_views, c)]);
         const int64_t npix = (int64_t)bv.W * bv.H;
         const int64_t p0 = (int64_t)(c - bv.px_chunk_off) * kBatchChunk +
                            4 * (int64_t)threadIdx.x;

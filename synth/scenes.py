@@ -318,20 +318,24 @@ FILTER_FULLHD = dict(radius=15, sigma_s=6.0, sigma_r=15.0)
 
 def small_view(rng: np.random.Generator, width=320, height=240,
                n_points: Optional[int] = None, n_beams=16, n_az=1800,
-               elev_deg=15.0) -> Frame:
+               elev_deg=15.0, noise_rng: Optional[np.random.Generator] = None) -> Frame:
     """6 axis-aligned boxes at depths U(1,20) m, no back wall, base colour +
     N(0,8) pixel noise, one 16-beam 360-degree sweep from 0.3 m away.
 
     With ``n_points`` set the sweep is confined to the camera's field of view
     and densified until about that many points hit (the widened scan used by
     the batched workload); the merged cloud is then cut to ``n_points``.
+    With ``noise_rng`` the pixel and range noise come from it and everything
+    else from ``rng``: frames with the same ``rng`` seed and different noise
+    generators are one static scene seen with fresh noise.
     """
+    noise = rng if noise_rng is None else noise_rng
     cam = Camera.pinhole(width, height)
     scene = make_scene(rng, cam, 6, back_wall=None, textured=False)
-    rgb, gt = render(scene, cam, rng)
+    rgb, gt = render(scene, cam, noise)
     origin = _random_offset(rng, 0.3, exact=True)
     if n_points is None:
-        pts = lidar_sweep(scene, rng, origin, n_beams, elev_deg, n_az)
+        pts = lidar_sweep(scene, noise, origin, n_beams, elev_deg, n_az)
     else:
         cover = max(float((gt > 0).mean()), 0.02)
         rays = int(n_points / cover * 1.15) + 64
@@ -339,7 +343,7 @@ def small_view(rng: np.random.Generator, width=320, height=240,
         vfov = math.degrees(math.atan((height / 2.0) / cam.fy)) * 1.05
         beams = max(8, int(round(math.sqrt(rays * vfov / hfov))))
         az = max(16, int(math.ceil(rays / beams)))
-        pts = lidar_sweep(scene, rng, origin, beams, vfov, az,
+        pts = lidar_sweep(scene, noise, origin, beams, vfov, az,
                           az_range_deg=(-hfov, hfov))
         pts = pts[:n_points]
     frame = Frame(pts, rgb, cam, gt, np.zeros(len(pts), np.int8),
@@ -479,6 +483,16 @@ def serving_view(spec) -> Frame:
     w, h, n, seed = spec
     rng = np.random.default_rng(seed)
     return with_random_pose(small_view(rng, w, h, n_points=n), rng)
+
+
+def serving_frame(spec, k: int) -> Frame:
+    """Frame k of a serving viewpoint: the viewpoint's static scene, camera
+    and world pose (from the spec's seed) with pixel and LiDAR range noise
+    drawn afresh (the k-th generator spawned from the seed)."""
+    w, h, n, seed = spec
+    rng = np.random.default_rng(seed)
+    noise = np.random.default_rng(np.random.SeedSequence(seed).spawn(k + 1)[k])
+    return with_random_pose(small_view(rng, w, h, n_points=n, noise_rng=noise), rng)
 
 
 def arrival_times(rng: np.random.Generator, n_views: int, duration_s: float,

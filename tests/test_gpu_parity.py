@@ -372,6 +372,51 @@ def test_filter_list_overflow_falls_back(torch_dev, frac):
                  max_samples=int(int(b.sum()) * frac))
 
 
+def _patchy(rng, h, w, density, patch):
+    """tiny_random plus a fully valid square patch (y0, x0, edge)."""
+    d, b, rgb = S.tiny_random(rng, h, w, density, n_colors=5)
+    y0, x0, e = patch
+    b[y0:y0 + e, x0:x0 + e] = 1
+    d = np.where(b == 1, np.where(d > 0, d, np.float32(7.5)), np.float32(0.0))
+    return d.astype(np.float32), b, rgb
+
+
+STAGE_CASES = [
+    # h, w, r, density, patch (y0, x0, edge) or None: what the halo staging
+    # of the list-free filter meets
+    (70, 90, 5, 0.30, None),            # tiles staged (about 200 samples each)
+    (70, 90, 5, 0.45, None),            # most tiles over the tile capacity
+    (70, 90, 5, 0.02, (20, 20, 12)),    # one block's halo over its capacity
+    (70, 90, 2, 0.60, None),            # small halo, dense
+    (90, 120, 15, 0.05, None),          # nine rounds per tile
+    (100, 100, 32, 0.02, None),         # 25 rounds per tile
+    (19, 300, 5, 0.20, (0, 250, 19)),   # partial tiles at the bottom edge
+]
+
+
+@pytest.mark.parametrize("case", STAGE_CASES,
+                         ids=[f"{c[0]}x{c[1]}r{c[2]}d{c[3]}" for c in STAGE_CASES])
+def test_filter_halo_staging(torch_dev, case):
+    """Without sample lists each workgroup stages its tile's halo once and
+    hands every wave its block's samples; past the capacities (256 samples
+    per tile halo, 128 per block halo) a wave streams its own halo. Every
+    case matches the oracle and the list path."""
+    torch, dev = torch_dev
+    h, w, r, dens, patch = case
+    rng = np.random.default_rng(h * 1000 + w + r)
+    if patch is None:
+        d, b, rgb = S.tiny_random(rng, h, w, dens, n_colors=5)
+    else:
+        d, b, rgb = _patchy(rng, h, w, dens, patch)
+    out, mask, _ = check_filter(torch, dev, d, b, rgb, r, 3.0, 12.0, ws=None)
+    lo, lm = _gpu_densify(torch, dev, d, b, rgb, r, 3.0, 12.0)
+    np.testing.assert_array_equal(mask, lm)
+    sel = mask == 1
+    if sel.any():
+        rel = np.abs(out[sel].astype(np.float64) - lo[sel]) / lo[sel]
+        assert rel.max() <= 2e-6
+
+
 def test_filter_paths_agree(torch_dev):
     torch, dev = torch_dev
     f = S.small_view(S.seeded(1))
