@@ -591,7 +591,6 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
         static_cast<unsigned char *>(host_table) + sizeof(jbfd::BatchHeader));
     int64_t tiles = 0, px_chunks = 0, pt_chunks = 0, units = 0;
     int64_t fpx = 0, fpt = 0, ftile = 0;   // items of the one-launch run
-    int64_t band[jbfd::kXcds] = {0};        // tiles per column band
     int32_t max_radius = 0;
     for (int32_t v = 0; v < n_views; ++v) {
         const jbfd_view &x = views[v];
@@ -646,12 +645,6 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
         b.ftile_off = (int32_t)ftile;
         ftile += (b.n_tiles + jbfd::kFusedTiles - 1) / jbfd::kFusedTiles;
         b.pad_ = 0;
-        const int64_t tiles_y = b.n_tiles / b.tiles_x;
-        for (int c = 0; c < jbfd::kXcds; ++c) {
-            b.band_off[c] = (int32_t)band[c];
-            const int64_t ncol = b.tiles_x > c ? (b.tiles_x - c + jbfd::kXcds - 1) / jbfd::kXcds : 0;
-            band[c] += ncol * tiles_y;
-        }
         if (x.radius > max_radius) max_radius = x.radius;
         // sample lists (as jbfd_densify with a workspace)
         const jbfd::ListLayout L = jbfd::list_layout(x.K.height, x.K.width);
@@ -696,8 +689,6 @@ jbfd_status jbfd_batch_prepare(const jbfd_view *views, int32_t n_views,
     hdr->exited = 0;
     hdr->error = 0;
     hdr->pad_ = 0;
-    for (int c = 0; c < jbfd::kXcds; ++c) hdr->band_tiles[c] = (int32_t)band[c];
-    hdr->pad2_[0] = hdr->pad2_[1] = 0;
     unsigned char *state = static_cast<unsigned char *>(host_table) +
                            jbfd::batch_queues_offset(n_views);
     memset(state, 0, jbfd_batch_table_bytes(n_views) - jbfd::batch_queues_offset(n_views));

@@ -416,14 +416,19 @@ struct BlockWalker {
                 for (int u = 0; u < NG; ++u)
                     g[u] = *reinterpret_cast<const float *>(Gb + (lc - q[u * kRecWords + 4]));
                 __builtin_amdgcn_sched_barrier(0);
+                // every colour dot first: a dot product's result is read
+                // by the next VALU instruction only after wait states,
+                // which the other samples' dots fill (61.5 against 62.8 us)
+                float tt[NG];
 #pragma unroll
                 for (int u = 0; u < NG; ++u) {
                     const uint32_t *qq = q + u * kRecWords;
-                    const float t =
-                        dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+                    tt[u] = dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
                     d[u] = __uint_as_float(qq[2]);
-                    sa[u] = stage_a(t, g[u], d[u]);
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < NG; ++u) sa[u] = stage_a(tt[u], g[u], d[u]);
                 __builtin_amdgcn_sched_barrier(0);
                 // the next group (the last full group again at the end, so
                 // the address stays inside the range)

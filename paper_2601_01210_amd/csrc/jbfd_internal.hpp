@@ -103,14 +103,7 @@ struct BatchView {
     int32_t fpt_off;
     int32_t ftile_off;
     int32_t pad_;
-    // launch-sequence filter: XCD c takes the tile columns tx = c (mod
-    // kXcds) of every view; band_off[c] is the exclusive prefix over the
-    // views of their tiles in those columns
-    int32_t band_off[8];
 };
-
-// XCDs of the chip: workgroup w of a launch runs on XCD w mod kXcds
-constexpr int kXcds = 8;
 
 // Elements (pixels or points) one workgroup handles per chunk of the
 // launch-sequence batch.
@@ -140,8 +133,6 @@ struct BatchHeader {
     uint32_t exited;        // workgroups that have finished
     uint32_t error;         // kBatchErr* bits of the runs since preparation
     uint32_t pad_;
-    int32_t band_tiles[8];  // tiles in the columns of XCD c over all views
-    uint32_t pad2_[2];
 };
 
 // error bits of a batch run
