@@ -637,32 +637,32 @@ struct BlockWalker {
 // with the clamped exponent -ks (dx^2+dy^2) >= -60 inside the window and
 // -inf outside (weights = false), or with the weight exp2(-ks (dx^2+dy^2))
 // floored at 2^-100 inside and 0 outside (weights = true).
+// The entries depend on |dx| and |dy| only: the workgroup's threads share
+// the quarter 0 <= |dx|, |dy| <= r + 7 and each writes its entry at the
+// four mirrored positions (about half the work of one entry per table
+// cell; the table is built by every workgroup, 8,160 times per Full-HD
+// frame). (float)(dx^2 + dy^2) is exact (below 2^24), so the entries equal
+// -ks (float)(dx^2 + dy^2), the exact pass's spatial exponents.
 __device__ inline void build_table(float *G, int r, int ts, float ks, bool weights) {
-    const int tdim = 2 * r + 15;
-    const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // a lane owns a column (dx), a wave walks rows (dy uniform): a row
-    // outside the window is stored without arithmetic, and inside it an
-    // entry costs one add, the exponent, its clamp and a select.
-    // (float)dx^2 + (float)dy^2 is exact (both below 2^24), so the entries
-    // equal -ks (float)(dx^2 + dy^2), the exact pass's spatial exponents.
+    const int h = r + 7;       // the centre's index in both directions
+    const int q = h + 1;       // quarter side
     const float g_out = weights ? 0.0f : -__builtin_inff();
-    for (int ux = lane; ux < tdim; ux += 64) {
-        const int dx = ux - r - 7;
-        const bool in_x = dx >= -r && dx <= r;
-        const float fx = (float)(dx * dx);
-        for (int uy = wid; uy < tdim; uy += 4) {
-            const int dy = uy - r - 7;
-            float g = g_out;
-            if (dy >= -r && dy <= r) {   // wave-uniform
-                const float e = -ks * (fx + (float)(dy * dy));
-                if (!weights)
-                    g = in_x ? fmaxf(e, kClampExp) : g_out;
-                else
-                    g = in_x ? __builtin_amdgcn_exp2f(fmaxf(e, -100.0f)) : g_out;
-            }
-            G[uy * ts + ux] = g;
+    // (e + 0.5) / q lies at least 0.5 / q from an integer, far above the
+    // product's rounding error for e < q^2 <= 1600
+    const float inv = __builtin_amdgcn_rcpf((float)q);
+    for (int e = (int)threadIdx.x; e < q * q; e += 256) {
+        const int ay = (int)(((float)e + 0.5f) * inv);
+        const int ax = e - ay * q;
+        float g = g_out;
+        if (ax <= r && ay <= r) {
+            const float d2 = -ks * (float)(ax * ax + ay * ay);
+            g = weights ? __builtin_amdgcn_exp2f(fmaxf(d2, -100.0f)) : fmaxf(d2, kClampExp);
         }
+        float *row0 = G + (h - ay) * ts, *row1 = G + (h + ay) * ts;
+        row0[h - ax] = g;
+        row0[h + ax] = g;
+        row1[h - ax] = g;
+        row1[h + ax] = g;
     }
 }
 
