@@ -709,7 +709,7 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
 // workgroup: builds the spatial table, then each wave filters its 8x8 block.
 // Every thread returns normally, so callers may loop over tiles with a
 // barrier between them.
-template <int RMAX, int PREC, bool STAGE>
+template <int RMAX, int PREC, bool STAGE, bool DIRECT = false>
 __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
                             const uint8_t *__restrict__ B,
                             const uint8_t *__restrict__ rgb, int H, int W,
@@ -761,7 +761,8 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     const BlockWalker bw{D, B, rgb, H, W, r, la, bx, by, lane, prg, pb0, lxy,
                          gstride, lc, ts,
                          reinterpret_cast<const unsigned char *>(sh.G),
-                         sh.recs[wid], sh.nq2h[wid], -fp.ks, staged};
+                         sh.recs[wid], sh.nq2h[wid], -fp.ks, staged,
+                         DIRECT ? nh : 0.0f};
 
     // Pass 1: fixed per-lane shift. Every exponent E = -kr c - ks s is <= 0,
     // so a = fma(2kr, t, -kr|p|^2) + G (the fma rounds once, relative to the
@@ -777,7 +778,34 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     //        (never zero in the window) decides the mask.
     const float Mfast = -fp.kr * p2;
     float num = 0.0f, den = 0.0f, dsp = 0.0f;
-    if constexpr (PREC == JBFD_FP32) {
+    if constexpr (PREC == JBFD_FP32 && DIRECT) {
+        // Without aux (no backward to serve): the walker starts each
+        // sample's colour term at -(|p|^2 + |q|^2)/2, so t = -c/2 exactly and
+        // one fma gives the exact exponent -kr c + G (G from the table, -inf
+        // outside the window), rounded once and never above 0. No clamp:
+        // a weight may underflow, so the mask comes from the sums: a lane
+        // whose sum stays below 2^-16, zero included, takes the exact pass,
+        // which decides it (one instruction less per sample than the
+        // clamped form).
+        auto stage_a = [&](float t, float g, float) { return __builtin_fmaf(kr2, t, g); };
+        auto stage_b = [&](float a, float, float d) {
+            const float w = __builtin_amdgcn_exp2f(a);
+            num = __builtin_fmaf(w, d, num);
+            den += w;
+        };
+        auto eat = [&](float t, float g, float d, uint32_t) {
+            stage_b(stage_a(t, g, d), g, d);
+        };
+        bw.template walk_split<true>(
+            stage_a, stage_b,
+            [&](const float (&t)[4], const float (&g)[4], const float (&d)[4],
+                const uint32_t (&uv)[4]) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) eat(t[u], g[u], d[u], uv[u]);
+            },
+            eat, -__builtin_inff());
+        dsp = den;
+    } else if constexpr (PREC == JBFD_FP32) {
         const Pass1Exp p1(kr2, Mfast);
         auto stage_a = [&](float t, float g, float) { return p1(t, g); };
         auto stage_b = [&](float a, float, float d) {
@@ -833,7 +861,9 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     // (clamping or precision could matter there): the exact running shift
     // of consume4/consume1 over the same samples, with exact, unclamped
     // spatial exponents.
-    const bool weak = inside && dsp > 0.0f && den < kWeakBelow;
+    // (DIRECT: also lanes whose sum is zero, whose window may hold samples
+    // whose weights all underflowed)
+    const bool weak = inside && (DIRECT || dsp > 0.0f) && den < kWeakBelow;
     float M = Mfast;
     if (__builtin_amdgcn_ballot_w64(weak) != 0) {
         float M2 = kShiftInit - fp.kr * p2, num2 = 0.0f, den2 = 0.0f;
@@ -856,6 +886,7 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
             num = num2;
             den = den2;
             M = M2;
+            if constexpr (DIRECT) dsp = den2;
         }
     }
 
@@ -870,7 +901,7 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     }
 }
 
-template <int RMAX, int PREC, bool STAGE>
+template <int RMAX, int PREC, bool STAGE, bool DIRECT>
 __global__ __launch_bounds__(256) void k_jbf_fwd(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, FilterParams fp,
@@ -880,7 +911,8 @@ __global__ __launch_bounds__(256) void k_jbf_fwd(
     int tx, ty;
     if (!column_tile(blockIdx.x, tiles_x, tiles_y, tx, ty))
         return;  // whole workgroup leaves together
-    filter_tile<RMAX, PREC, STAGE>(D, B, rgb, H, W, fp, la, tx, ty, out, mask, aux, sh);
+    filter_tile<RMAX, PREC, STAGE, DIRECT>(D, B, rgb, H, W, fp, la, tx, ty, out, mask,
+                                           aux, sh);
 }
 
 hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
@@ -922,10 +954,17 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
     float2 *a2 = reinterpret_cast<float2 *>(aux);
     // with sample lists no staging (its LDS would cost the list walk
     // occupancy); without, the workgroup stages each tile's halo
+    // FP32 without aux takes the direct first pass (clamped weights only
+    // when the backward needs them)
     auto go = [&](auto rmax, auto prc, auto stage, float2 *ax) {
-        k_jbf_fwd<decltype(rmax)::value, decltype(prc)::value, decltype(stage)::value>
-            <<<n_wg, 256, 0, s>>>(D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out,
-                                  mask, ax);
+        constexpr int R = decltype(rmax)::value, PR = decltype(prc)::value;
+        constexpr bool ST = decltype(stage)::value;
+        if (PR == JBFD_FP32 && ax == nullptr)
+            k_jbf_fwd<R, PR, ST, PR == JBFD_FP32><<<n_wg, 256, 0, s>>>(
+                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, ax);
+        else
+            k_jbf_fwd<R, PR, ST, false><<<n_wg, 256, 0, s>>>(
+                D, B, rgb, H, W, fp, tiles_x, tiles_y, la, out, mask, ax);
     };
     using F32 = std::integral_constant<int, JBFD_FP32>;
     using F16 = std::integral_constant<int, JBFD_FP16_RANGE>;
@@ -1031,8 +1070,9 @@ __global__ __launch_bounds__(256) void k_batch_filter(BatchHeader *__restrict__ 
         if (rebuild && cur_r >= 0) __syncthreads();  // old table no longer read
         // lists only when this run built them (recs null: stream)
         const ListArgs la{use_lists ? v.recs : nullptr, v.rowoff, v.capacity};
-        filter_tile<RMAX, PREC, STAGE>(v.sd, v.sv, v.rgb, v.H, v.W, fp, la, tx, ty,
-                                       v.out, v.mask, nullptr, sh, rebuild);
+        filter_tile<RMAX, PREC, STAGE, PREC == JBFD_FP32>(v.sd, v.sv, v.rgb, v.H, v.W,
+                                                          fp, la, tx, ty, v.out, v.mask,
+                                                          nullptr, sh, rebuild);
         cur_r = fp.radius;
         cur_ks = fp.ks;
     }
@@ -1336,7 +1376,8 @@ void k_batch_fused(BatchHeader *__restrict__ hdr, const BatchView *__restrict__ 
                 bool rebuild = fp.radius != cur_r || fp.ks != cur_ks;
                 const ListArgs none{nullptr, nullptr, 0};
                 for (int lt = t0; lt < min(t0 + kFusedTiles, bv.n_tiles); ++lt) {
-                    filter_tile<RMAX, PREC, true>(bv.sd, bv.sv, bv.rgb, bv.H, bv.W, fp, none,
+                    filter_tile<RMAX, PREC, true, PREC == JBFD_FP32>(
+                        bv.sd, bv.sv, bv.rgb, bv.H, bv.W, fp, none,
                                             lt % bv.tiles_x, lt / bv.tiles_x, bv.out,
                                             bv.mask, nullptr, sh, rebuild);
                     rebuild = false;

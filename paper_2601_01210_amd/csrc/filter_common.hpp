@@ -300,6 +300,17 @@ struct BlockWalker {
     float nks;             // -ks
     int staged = -1;       // samples of the block's halo that the workgroup
                            // staged into `my` (row-major), or -1: stream
+    float tadd = 0.0f;     // added to each sample's -|q|^2/2 when ADD
+
+    // start of a sample's colour term: -|q|^2/2, plus the lane's own
+    // -|p|^2/2 when ADD (then t = -c/2 exactly, c the squared distance)
+    template <bool ADD>
+    __device__ float tinit(float q2h) const {
+        if constexpr (ADD)
+            return q2h + tadd;
+        else
+            return q2h;
+    }
 
     // exact spatial exponent: -ks (dx^2+dy^2) inside the window, -inf outside
     __device__ float exact_g(uint32_t u) const {
@@ -318,7 +329,7 @@ struct BlockWalker {
     }
 
     // samples held in the wave's LDS list
-    template <bool EXACT, class E4, class E1>
+    template <bool EXACT, bool ADD = false, class E4, class E1>
     __device__ void run_chunk(int cnt, E4 &eat4, E1 &eat1) const {
         int k = 0;
         for (; k + 4 <= cnt; k += 4) {
@@ -327,7 +338,7 @@ struct BlockWalker {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const Rec q = my[k + u];
-                t[u] = dot2h(prg, q.rg, dot2h(pb0, q.b0, myq[k + u]));
+                t[u] = dot2h(prg, q.rg, dot2h(pb0, q.b0, tinit<ADD>(myq[k + u])));
                 uv[u] = pk_sub_u16(lxy, q.xy);
                 g[u] = spatial<EXACT>(uv[u]);
                 d[u] = q.d;
@@ -336,7 +347,7 @@ struct BlockWalker {
         }
         for (; k < cnt; ++k) {
             const Rec q = my[k];
-            const float t = dot2h(prg, q.rg, dot2h(pb0, q.b0, myq[k]));
+            const float t = dot2h(prg, q.rg, dot2h(pb0, q.b0, tinit<ADD>(myq[k])));
             const uint32_t uv = pk_sub_u16(lxy, q.xy);
             eat1(t, spatial<EXACT>(uv), q.d, uv);
         }
@@ -398,7 +409,7 @@ struct BlockWalker {
     // (t, g, d) must use g; stage_b finishes the sample. The arithmetic is
     // the same as walk_list's with eat = stage_b o stage_a. g_none is the
     // table value of weight zero (-inf for exponents, 0 for weights).
-    template <class SA, class SB, class E1>
+    template <bool ADD = false, class SA, class SB, class E1>
     __device__ void walk_list_split(int lo, int hi, SA &stage_a, SB &stage_b,
                                     E1 &eat1, float g_none) const {
         const uint32_t *__restrict__ rp = la.recs;
@@ -423,7 +434,8 @@ struct BlockWalker {
 #pragma unroll
                 for (int u = 0; u < NG; ++u) {
                     const uint32_t *qq = q + u * kRecWords;
-                    tt[u] = dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+                    tt[u] = dot2h(prg, qq[0],
+                                  dot2h(pb0, qq[1], tinit<ADD>(__uint_as_float(qq[3]))));
                     d[u] = __uint_as_float(qq[2]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -451,8 +463,8 @@ struct BlockWalker {
 #pragma unroll
                 for (int u = 0; u < NG; ++u) {
                     const uint32_t *qq = q + u * kRecWords;
-                    const float t =
-                        dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+                    const float t = dot2h(
+                        prg, qq[0], dot2h(pb0, qq[1], tinit<ADD>(__uint_as_float(qq[3]))));
                     const float gt =
                         *reinterpret_cast<const float *>(Gb + (lc - qq[4]));
                     const float g = u < skip ? g_none : gt;
@@ -465,7 +477,8 @@ struct BlockWalker {
         // lists of fewer than NG samples
         for (; k < hi; ++k) {
             const uint32_t *qq = rp + (int64_t)k * kRecWords;
-            const float t = dot2h(prg, qq[0], dot2h(pb0, qq[1], __uint_as_float(qq[3])));
+            const float t =
+                dot2h(prg, qq[0], dot2h(pb0, qq[1], tinit<ADD>(__uint_as_float(qq[3]))));
             const uint32_t off = lc - qq[4];
             eat1(t, *reinterpret_cast<const float *>(Gb + off), __uint_as_float(qq[2]),
                  off);
@@ -519,19 +532,19 @@ struct BlockWalker {
     }
 
     // first pass: the split list walk, or the stream
-    template <class SA, class SB, class E4, class E1>
+    template <bool ADD = false, class SA, class SB, class E4, class E1>
     __device__ void walk_split(SA &&stage_a, SB &&stage_b, E4 &&eat4, E1 &&eat1,
                                float g_none) const {
         int lo, hi;
         if (list_range(lo, hi)) {
-            walk_list_split(lo, hi, stage_a, stage_b, eat1, g_none);
+            walk_list_split<ADD>(lo, hi, stage_a, stage_b, eat1, g_none);
             return;
         }
         if (staged >= 0) {
-            run_chunk<false>(staged, eat4, eat1);
+            run_chunk<false, ADD>(staged, eat4, eat1);
             return;
         }
-        stream<false>(eat4, eat1);
+        stream<false, ADD>(eat4, eat1);
     }
 
     // ---- stream the block's halo from the images ----
@@ -541,7 +554,7 @@ struct BlockWalker {
     // strides (plus a row wrap), and addresses the images with 32-bit
     // offsets from their bases (every offset of an image of at most
     // JBFD_MAX_SIDE^2 pixels, times 4, fits in 32 bits).
-    template <bool EXACT, class E4, class E1>
+    template <bool EXACT, bool ADD = false, class E4, class E1>
     __device__ void stream(E4 &eat4, E1 &eat1) const {
         const int hx0 = max(bx - r, 0), hx1 = min(bx + 8 + r, W);
         const int hy0 = max(by - r, 0), hy1 = min(by + 8 + r, H);
@@ -622,7 +635,7 @@ struct BlockWalker {
             const uint32_t p2n = pix(base + 128);
             const uint32_t m2 = B[p2n];
             __builtin_amdgcn_wave_barrier();
-            run_chunk<EXACT>(cnt, eat4, eat1);
+            run_chunk<EXACT, ADD>(cnt, eat4, eat1);
             __builtin_amdgcn_wave_barrier();
             stage(v1, bal1, xy1, c01, c2, d1);
             cnt = __builtin_popcountll(bal1);
@@ -655,7 +668,7 @@ __device__ inline void build_table(float *G, int r, int ts, float ks, bool weigh
         const int ax = e - ay * q;
         float g = g_out;
         if (ax <= r && ay <= r) {
-            const float d2 = -ks * (float)(ax * ax + ay * ay);
+            const float d2 = -ks * (float)(__mul24(ax, ax) + __mul24(ay, ay));
             g = weights ? __builtin_amdgcn_exp2f(fmaxf(d2, -100.0f)) : fmaxf(d2, kClampExp);
         }
         float *row0 = G + (h - ay) * ts, *row1 = G + (h + ay) * ts;
