@@ -285,9 +285,9 @@ jbfd_status jbfd_zbuf_clear(uint64_t *zbuf, int32_t H, int32_t W, void *stream);
  *                 n bounds the number of valid samples (the number of
  *                 projected points is such a bound), the call first builds
  *                 per-strip sample lists and the filter reads them; with a
- *                 smaller or no workspace, or if the image holds more valid
- *                 samples than the workspace can list, the filter streams
- *                 the inputs directly. Both ways visit the samples in the
+ *                 smaller or no workspace, if the image holds more valid
+ *                 samples than the workspace can list, or if it has more
+ *                 than 2^26 pixels, the filter streams the inputs directly. Both ways visit the samples in the
  *                 same (row-major) order; they may differ in the last bits
  *                 where a range rescale falls inside a group of samples.
  */
@@ -531,7 +531,12 @@ jbfd_status jbfd_remove_occluded(const float *sparse_depth,
  * count      device int64: the number of points written
  * ws         device, 256-byte aligned, jbfd_backproject_ws_bytes(H, W)
  *            bytes (else JBFD_ENOSPC)
+ * H*W at most JBFD_BACKPROJECT_MAX_PIXELS (else JBFD_EINVAL; the write pass
+ * sums the point counts of all earlier 1024-pixel chunks in every chunk, a
+ * cost that grows with the square of the image size: about 1 ms at the
+ * limit); jbfd_backproject_ws_bytes returns 0 beyond it.
  */
+#define JBFD_BACKPROJECT_MAX_PIXELS (1 << 26)
 size_t jbfd_backproject_ws_bytes(int32_t H, int32_t W);
 jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_valid,
                              const uint8_t *rgb_hwc, int32_t H, int32_t W,

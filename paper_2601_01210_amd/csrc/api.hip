@@ -484,7 +484,9 @@ jbfd_status jbfd_remove_occluded(const float *sparse_depth,
 }
 
 size_t jbfd_backproject_ws_bytes(int32_t H, int32_t W) {
-    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE) return 0;
+    if (H <= 0 || W <= 0 || H > JBFD_MAX_SIDE || W > JBFD_MAX_SIDE ||
+        (int64_t)H * W > JBFD_BACKPROJECT_MAX_PIXELS)
+        return 0;
     return jbfd::backproject_ws_bytes(H, W);
 }
 
@@ -499,6 +501,9 @@ jbfd_status jbfd_backproject(const float *dense_depth, const uint8_t *dense_vali
         return fail(JBFD_EINVAL, "jbfd_backproject: null buffer");
     jbfd_status st = check_image(H, W);
     if (st != JBFD_OK) return st;
+    if ((int64_t)H * W > JBFD_BACKPROJECT_MAX_PIXELS)
+        return fail(JBFD_EINVAL, "jbfd_backproject: %d x %d pixels above the limit %d", H,
+                    W, JBFD_BACKPROJECT_MAX_PIXELS);
     if (K->width != W || K->height != H)
         return fail(JBFD_EINVAL, "jbfd_backproject: intrinsics size %d x %d != image",
                     K->width, K->height);

@@ -164,10 +164,18 @@ inline ListLayout list_layout(int H, int W) {
 // Largest number of strips whose halo columns hold one image column.
 inline int strips_per_column(int r) { return (2 * r + 7) / 8 + 1; }
 
+// Largest image (pixels) that gets sample lists: the list scatter's
+// workgroups each sum the record counts of all earlier (group, band) units,
+// a cost that grows with the square of the unit count (one unit per 1,024
+// pixels; about 1 ms at this size). Larger images stream their halos.
+constexpr int64_t kListMaxPixels = (int64_t)1 << 26;
+
 // Record indices are int32: lists are built only when every pixel of the
-// image could be valid without overflowing them.
+// image could be valid without overflowing them, and only up to
+// kListMaxPixels.
 inline bool lists_possible(int H, int W, int r) {
-    return (int64_t)H * W * strips_per_column(r) < ((int64_t)1 << 31);
+    return (int64_t)H * W * strips_per_column(r) < ((int64_t)1 << 31) &&
+           (int64_t)H * W <= kListMaxPixels;
 }
 
 struct ListArgs {

@@ -321,6 +321,14 @@ def test_occlusion_and_backproject_reject_bad_arguments(L):
     zero.fx = 0.0
     assert call(zero, 0.05, ws, n) == JBFD_EINVAL
     assert call(K, 0.05, C.c_void_p(0x10004), n) == JBFD_EINVAL
+    # images above 2^26 pixels are refused (the write pass's chunk prefix
+    # grows with the square of the image size)
+    assert L.jbfd_backproject_ws_bytes(8192, 8192) > 0
+    assert L.jbfd_backproject_ws_bytes(8193, 8193) == 0
+    big = _K(8193, 8193)
+    assert L.jbfd_backproject(fake, fake, fake, 8193, 8193, pose, C.byref(big), 0.05,
+                              fake, fake, fake, ws, 1 << 40, None) == JBFD_EINVAL
+    assert b"limit" in L.jbfd_last_error()
 
 
 def test_afterimage_entry_points_reject_bad_arguments(L):
