@@ -115,7 +115,9 @@ constexpr int kBatchChunk = 1024;
 constexpr int kFusedPxChunk = 2048;   // pixels per decode item
 constexpr int kFusedPtChunk = 512;    // points per projection item
 constexpr int kFusedTiles = 4;        // filter tiles per item (one row run)
-constexpr int kQueues = 16;           // work queues, workgroup w uses w % kQueues
+// work queues, workgroup w uses w % kQueues (16, 32, 64 and 128 queues
+// measured 0.256, 0.250-0.255, 0.251 and 0.259 ms on the eight-view batch)
+constexpr int kQueues = 64;
 constexpr int kQueueRun = 4;          // consecutive items per queue turn
 
 struct BatchHeader {

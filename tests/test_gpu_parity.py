@@ -417,6 +417,41 @@ def test_filter_halo_staging(torch_dev, case):
         assert rel.max() <= 2e-6
 
 
+@pytest.mark.parametrize("case", [(60, 90, 5, 0.08, 3.0, 12.0, 5),
+                                  (70, 100, 15, 0.05, 6.0, 15.0, 6),
+                                  (50, 66, 5, 0.08, 0.25, 0.25, 8)],
+                         ids=["r5", "r15", "tiny-sigmas"])
+def test_filter_direct_and_clamped_forms(torch_dev, case):
+    """FP32 without aux forms each exponent exactly with one fma and lets
+    weights underflow (lanes whose sum ends below 2^-16, zero included, take
+    the exact pass); with aux it keeps the clamped weights the backward
+    replays. Both match the oracle and each other (mask bit for bit), on the
+    list and the stream path."""
+    torch, dev = torch_dev
+    from paper_2601_01210_amd import densify
+    h, w, r, dens, ss, sr, pal = case
+    d, b, rgb = S.tiny_random(np.random.default_rng(h * w + r), h, w, dens, n_colors=pal)
+    ref, rmask = oracle.densify(d, b, rgb, r, ss, sr)
+    td = torch.from_numpy(d).to(dev)
+    tb = torch.from_numpy(b).to(dev)
+    tc = torch.from_numpy(rgb).to(dev)
+    sel = rmask == 1
+    for ws in ("auto", None):
+        o1, m1 = densify(td, tb, tc, r, ss, sr, ws=ws, max_samples=int(b.sum()))
+        o2, m2, _ = densify(td, tb, tc, r, ss, sr, want_aux=True, ws=ws,
+                            max_samples=int(b.sum()))
+        torch.cuda.synchronize()
+        for o, m in ((o1, m1), (o2, m2)):
+            o, m = o.cpu().numpy(), m.cpu().numpy()
+            np.testing.assert_array_equal(m, rmask)
+            if sel.any():
+                rel = np.abs(o[sel].astype(np.float64) - ref[sel]) / ref[sel]
+                assert rel.max() <= REL_TOL
+        a, c = o1.cpu().numpy(), o2.cpu().numpy()
+        if sel.any():
+            assert (np.abs(a[sel].astype(np.float64) - c[sel]) / c[sel]).max() <= 2e-6
+
+
 def test_filter_paths_agree(torch_dev):
     torch, dev = torch_dev
     f = S.small_view(S.seeded(1))
