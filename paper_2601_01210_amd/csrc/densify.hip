@@ -28,10 +28,12 @@
 // 16 bytes into each of the 64 lanes and make the filter LDS-bandwidth
 // bound. A block whose range does not fit the workspace streams instead.
 //
-// Without a workspace each wave streams the halo of its block from the input
-// images in 64-pixel chunks and compacts the valid samples into a
-// wave-private LDS list (software-pipelined: the mask bytes of chunk c+2
-// and the sample data of chunk c+1 load while chunk c is processed).
+// Without a workspace the workgroup stages its tile's halo once and each
+// wave copies its block's samples into its LDS list (tile_stage); beyond
+// the staging capacities a wave streams the halo of its block from the
+// input images in 64-pixel chunks and compacts the valid samples into its
+// list (software-pipelined: the mask bytes of chunk c+2 and the sample
+// data of chunk c+1 load while chunk c is processed).
 //
 // Per sample and lane (one output pixel):
 //   colour   t = p.q - |q|^2/2 by two v_dot2_f32_f16 on the 0..255 channel
@@ -41,17 +43,23 @@
 //            (2r+1)^2 window and -inf outside; a list record carries its
 //            position as a table offset, so the lane's address is one
 //            subtract and the window test is free;
-//   weight   w = exp2(max(2 kr t - kr|p|^2, -60) + G), kr and ks in log2
+//   weight   FP32 without aux (the direct pass): the colour term starts at
+//            -(|p|^2 + |q|^2)/2, so t = -c/2 exactly and w = exp2(fma(2 kr,
+//            t, G)), eight VALU instructions per sample; a weight may
+//            underflow, so lanes whose sum ends below 2^-16, zero
+//            included, take the second pass, which also decides their
+//            mask. With aux (the backward replays these weights):
+//            w = exp2(max(2 kr t - kr|p|^2, -60) + G), kr and ks in log2
 //            units (the table is clamped at -60 too), so every in-window
 //            sample has w >= 2^-120 > 0 and den > 0 is exactly the mask;
-//            the clamp rides on an fma's output modifier (Pass1Exp), so
-//            a sample costs nine VALU instructions.
-// Lanes whose weight sum ends below 2^-16 (far colours: clamping or
-// rounding could matter) are recomputed in a second pass with an exact
-// running shift M: it starts at 2^23 - kr|p|^2 and drops by whole integers k
-// whenever an exponent would exceed +12, scaling the sums by 2^-k, with
-// unclamped spatial exponents. Every weight of a pixel is thus its true
-// value times one common factor, which cancels in num/den.
+//            the clamp rides on an fma's output modifier (Pass1Exp), nine
+//            instructions per sample.
+// Lanes whose weight sum ends below 2^-16 (far colours: clamping,
+// underflow or rounding could matter) are recomputed in a second pass with
+// an exact running shift M: it starts at 2^23 - kr|p|^2 and drops by whole
+// integers k whenever an exponent would exceed +12, scaling the sums by
+// 2^-k, with unclamped spatial exponents. Every weight of a pixel is thus
+// its true value times one common factor, which cancels in num/den.
 //
 // The fraction of (pixel, halo sample) pairs that fall inside the window is
 // (2r+1)^2/(2r+8)^2 (66% at r = 15).
