@@ -14,7 +14,7 @@
 // record {(r,g) f16x2, (b,0) f16x2, depth, -|rgb|^2 / 2, table word}. Two
 // kernels build all lists, each over (group of 8 strips) x (band of 16
 // rows) units:
-//   k_list_count    validity masks of the band's rows over the group's 128
+//   k_list_count    validity masks of the band's rows over the group's
 //                   halo columns (wave ballots) -> records per strip and band;
 //   k_list_scatter  the group's strip offsets from the band counts, per-row
 //                   offsets by a wave scan over the band's rows (written
@@ -73,19 +73,30 @@ size_t densify_ws_bytes(int32_t H, int32_t W, int32_t r, int64_t max_samples) {
     return L.recs + (size_t)max_samples * strips_per_column(r) * kRecWords * 4;
 }
 
+// The halo columns of group g at radius r are [c0, c0 + 64 + 2r) with
+// c0 = 64g - r, at most 128 (r <= 32): lane l covers column c0 + l in the
+// first half and column c0 + 64 + l in the second, where only lanes
+// l < 2r lie in the halo. The other lanes of the second half read the
+// halo's last column again (a load of a line the wave already reads) and
+// their ballot bits are zero.
+__device__ __forceinline__ int halo_col_b(int c0, int r, int W) {
+    const int lane = threadIdx.x & 63;
+    return min(c0 + 64 + min(lane, 2 * r - 1), W - 1);   // >= 0: r < 64
+}
+
 // Load the validity bytes of rows [y_first, y_first + NROWS) over the
-// group's 128 halo columns [c0, c0 + 128), one byte per lane and row for
-// columns c0 + lane and c0 + 64 + lane. Every load is unconditional from a
-// clamped (in-image) address, so all of them are in flight together;
-// row_ballots masks the columns and rows outside the image.
+// group's halo columns (halo_col_b), one byte per lane and row and half.
+// Every load is unconditional from a clamped (in-image) address, so all of
+// them are in flight together; row_ballots masks the columns and rows
+// outside the image and the halo.
 template <int NROWS>
 __device__ __forceinline__ void group_row_bytes(const uint8_t *__restrict__ B, int H,
-                                                int W, int c0, int y_first,
+                                                int W, int c0, int r, int y_first,
                                                 uint8_t (&va)[NROWS],
                                                 uint8_t (&vb)[NROWS]) {
     const int lane = threadIdx.x & 63;
     const int xa_c = min(max(c0 + lane, 0), W - 1);
-    const int xb_c = min(max(c0 + 64 + lane, 0), W - 1);
+    const int xb_c = halo_col_b(c0, r, W);
 #pragma unroll
     for (int k = 0; k < NROWS; ++k) {
         const uint8_t *row = B + (int64_t)min(y_first + k, H - 1) * W;
@@ -94,21 +105,34 @@ __device__ __forceinline__ void group_row_bytes(const uint8_t *__restrict__ B, i
     }
 }
 
-// ... and ballot them into 128-bit row masks
+// ... and ballot them into 128-bit row masks (bit c: column c0 + c)
 template <int NROWS>
-__device__ __forceinline__ void row_ballots(int H, int W, int c0, int y_first,
+__device__ __forceinline__ void row_ballots(int H, int W, int c0, int r, int y_first,
                                             const uint8_t (&va)[NROWS],
                                             const uint8_t (&vb)[NROWS],
                                             uint64_t (&lo)[NROWS], uint64_t (&hi)[NROWS]) {
     const int lane = threadIdx.x & 63;
     const int xa = c0 + lane, xb = c0 + 64 + lane;
-    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
+    const bool ina = xa >= 0 && xa < W, inb = lane < 2 * r && xb < W;
 #pragma unroll
     for (int k = 0; k < NROWS; ++k) {
         const bool iny = y_first + k < H;
         lo[k] = __builtin_amdgcn_ballot_w64(ina && iny && va[k] != 0);
         hi[k] = __builtin_amdgcn_ballot_w64(inb && iny && vb[k] != 0);
     }
+}
+
+// Unit (group g, band) of this workgroup in a one-dimensional grid of
+// n_groups x n_bands workgroups. Workgroup i runs on XCD i mod 8, each XCD
+// with an L2 of its own, and neighbouring groups of a band read each
+// other's edge columns, so the units are numbered band by band and XCD x
+// takes the x-th of eight contiguous runs of them.
+__device__ __forceinline__ void list_unit(int n_groups, int n_bands, int &g, int &band) {
+    const int n = n_groups * n_bands;
+    const int i = blockIdx.x, x = i & 7, slot = i >> 3;
+    const int u = x * (n >> 3) + min(x, n & 7) + slot;
+    band = u / n_groups;
+    g = u - band * n_groups;
 }
 
 // Records per (strip, band) from the row masks of the unit (group g, band
@@ -158,9 +182,9 @@ __device__ __forceinline__ void list_count_unit(const uint8_t *__restrict__ B, i
     constexpr int kRowsPerWave = kBandRows / 4;
     const int y_first = band * kBandRows + wid * kRowsPerWave;
     uint8_t va[kRowsPerWave], vb[kRowsPerWave];
-    group_row_bytes<kRowsPerWave>(B, H, W, c0, y_first, va, vb);
+    group_row_bytes<kRowsPerWave>(B, H, W, c0, r, y_first, va, vb);
     uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
-    row_ballots<kRowsPerWave>(H, W, c0, y_first, va, vb, lo, hi);
+    row_ballots<kRowsPerWave>(H, W, c0, r, y_first, va, vb, lo, hi);
     count_strips<kRowsPerWave>(lo, hi, r, n_strips, n_bands, bandcnt, grpcnt, g, band);
 }
 
@@ -169,13 +193,14 @@ __global__ __launch_bounds__(256) void k_list_count(const uint8_t *__restrict__ 
                                                     int n_bands,
                                                     int *__restrict__ bandcnt,
                                                     int *__restrict__ grpcnt) {
-    list_count_unit(B, H, W, r, n_strips, n_bands, bandcnt, grpcnt, blockIdx.x,
-                    blockIdx.y);
+    int g, band;
+    list_unit((n_strips + kGroupStrips - 1) / kGroupStrips, n_bands, g, band);
+    list_count_unit(B, H, W, r, n_strips, n_bands, bandcnt, grpcnt, g, band);
 }
 
 // Decode and count in one pass, for a projection straight into the sample
 // lists (jbfd_project_densify). Unit (group g, band b) reads the keys of the
-// band's rows over the group's 128 halo columns, writes depth and validity
+// band's rows over the group's halo columns, writes depth and validity
 // of its own 64 columns [64g, 64g + 64) (lane l decodes column
 // 64g + ((l - r) mod 64) of each row, from the key it loaded in the first
 // or the second half; r <= 32 < 64) and counts each strip's samples as
@@ -187,14 +212,15 @@ __global__ __launch_bounds__(256) void k_decode_count(const uint64_t *__restrict
                                                       uint8_t *__restrict__ B,
                                                       int *__restrict__ bandcnt,
                                                       int *__restrict__ grpcnt) {
-    const int g = blockIdx.x, band = blockIdx.y;
+    int g, band;
+    list_unit((n_strips + kGroupStrips - 1) / kGroupStrips, n_bands, g, band);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int c0 = 64 * g - r;
     constexpr int kRowsPerWave = kBandRows / 4;
     const int y_first = band * kBandRows + wid * kRowsPerWave;
     const int xa = c0 + lane, xb = c0 + 64 + lane;
-    const int xa_c = min(max(xa, 0), W - 1), xb_c = min(max(xb, 0), W - 1);
+    const int xa_c = min(max(xa, 0), W - 1), xb_c = halo_col_b(c0, r, W);
     uint64_t ka[kRowsPerWave], kb[kRowsPerWave];
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) {   // all loads in flight together
@@ -202,7 +228,7 @@ __global__ __launch_bounds__(256) void k_decode_count(const uint64_t *__restrict
         ka[k] = row[xa_c];
         kb[k] = row[xb_c];
     }
-    const bool ina = xa >= 0 && xa < W, inb = xb >= 0 && xb < W;
+    const bool ina = xa >= 0 && xa < W, inb = lane < 2 * r && xb < W;
     uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
 #pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) {
@@ -230,16 +256,18 @@ __global__ __launch_bounds__(256) void k_decode_count(const uint64_t *__restrict
 // Offsets and records of the group's strips over one band (see the file
 // comment). The absolute start of strip s is the sum of the band counts of
 // every strip before it; the start of band b within s adds the counts of
-// bands < b.
+// bands < b. The phases are ordered so that the loads of the records' data
+// are in flight while the offsets are computed: masks, the band's valid
+// pixels (plist) and their colour and depth loads first, then the offsets,
+// then the record stores.
 __device__ __forceinline__ void list_scatter_unit(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
     int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
     int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs, int g,
-    int band) {
+    int band, uint64_t *__restrict__ reset_keys = nullptr) {
     __shared__ uint64_t mlo[kBandRows], mhi[kBandRows];
     __shared__ __align__(16) int start[kBandRows][kGroupStrips];   // [row][strip]
-    __shared__ int rowpos[kBandRows + 1];
     __shared__ uint16_t plist[kBandRows * 128];   // valid pixels of the band
 
     __shared__ int red[4];
@@ -251,18 +279,18 @@ __device__ __forceinline__ void list_scatter_unit(
     const int y_band = band * kBandRows;
     const int s_first = kGroupStrips * g;
 
-    // The prologue's loads are all issued before the first wait: (3) the
-    // validity bytes of the band's rows (wave w: rows 4w .. 4w+3), (1) the
+    // The prologue's loads are all issued before the first wait: (a) the
+    // validity bytes of the band's rows (wave w: rows 4w .. 4w+3), (b) the
     // group-and-band totals of the groups before g, whose sum is the number
-    // of records of all strips before the group, and (2) per strip of the
+    // of records of all strips before the group, and (c) per strip of the
     // group (32 threads each), its band counts, for its total and the part
-    // in bands before ours. One batch of (1) and (2) covers images of up to
+    // in bands before ours. One batch of (b) and (c) covers images of up to
     // 2048 group-band entries before the group and 128 bands (Full-HD:
     // 1972 and 68); larger images loop over further batches afterwards.
     constexpr int kRowsPerWave = kBandRows / 4;
     const int y_rows = y_band + wid * kRowsPerWave;
     uint8_t va[kRowsPerWave], vb[kRowsPerWave];
-    group_row_bytes<kRowsPerWave>(B, H, W, c0, y_rows, va, vb);
+    group_row_bytes<kRowsPerWave>(B, H, W, c0, r, y_rows, va, vb);
     const int n_before = g * n_bands;
     int a[8];
 #pragma unroll
@@ -280,6 +308,78 @@ __device__ __forceinline__ void list_scatter_unit(
         const int b = 32 * u + k32;
         c[u] = bc[b < n_bands ? b : 0];
     }
+
+    // (1) row masks (waits for the validity bytes only)
+    {
+        uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
+        row_ballots<kRowsPerWave>(H, W, c0, r, y_rows, va, vb, lo, hi);
+        if (lane < kRowsPerWave) {
+            uint64_t ma = 0, mb = 0;
+#pragma unroll
+            for (int k = 0; k < kRowsPerWave; ++k) {
+                ma = lane == k ? lo[k] : ma;
+                mb = lane == k ? hi[k] : mb;
+            }
+            mlo[wid * kRowsPerWave + lane] = ma;
+            mhi[wid * kRowsPerWave + lane] = mb;
+        }
+    }
+    __syncthreads();
+    // (2) compact the band's valid pixels into plist (row << 8 | column),
+    // row by row; every wave scans the rows' counts (lane = row) and fills
+    // rows w, w + 4, ...
+    int total;
+    {
+        const bool rl = lane < kBandRows;
+        const int row = rl ? lane : 0;
+        const int cnt = rl ? __builtin_popcountll(mlo[row]) + __builtin_popcountll(mhi[row])
+                           : 0;
+        const int incl = wave_inclusive_scan(cnt);
+        const int excl = incl - cnt;
+        total = __builtin_amdgcn_readlane(incl, kBandRows - 1);
+        for (int row = wid; row < kBandRows; row += 4) {
+            const uint64_t ml = mlo[row], mh = mhi[row];
+            const int base = __builtin_amdgcn_readlane(excl, row);
+            const uint32_t below =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(ml >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ml, 0u));
+            if ((ml >> lane) & 1ull) plist[base + below] = (uint16_t)((row << 8) | lane);
+            const uint32_t below_h =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(mh >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mh, 0u));
+            if ((mh >> lane) & 1ull)
+                plist[base + __builtin_popcountll(ml) + below_h] =
+                    (uint16_t)((row << 8) | (64 + lane));
+        }
+    }
+    __syncthreads();
+    // (3) one thread per valid pixel, two per pass: the first pass's colour
+    // and depth loads are issued here, unconditionally (a lane past the end
+    // reads the band's first in-image pixel of the group), so no branch
+    // separates them from the offsets' waits below
+    const int safe_ent = c0 < 0 ? -c0 : 0;   // row 0, column max(c0, 0)
+    int ent[2];
+    uint32_t c01[2], c2[2], dd[2];
+    auto load_pass = [&](int e0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + 256 * u + t;
+            ent[u] = e < total ? (int)plist[e] : safe_ent;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = ent[u] >> 8, lc = ent[u] & 255;
+            const int64_t p = (int64_t)(y_band + row) * W + (c0 + lc);
+            const uint8_t *cp = rgb + 3 * p;
+            c01[u] = (uint32_t)cp[0] | ((uint32_t)cp[1] << 8);
+            c2[u] = cp[2];
+            dd[u] = __float_as_uint(D[p]);
+        }
+    };
+    load_pass(0);
+
+    // (4) the offsets: strip totals and parts before the band, the groups'
+    // sum, per-row counts of each strip
     int acc = 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc += 256 * u + t < n_before ? a[u] : 0;
@@ -332,19 +432,9 @@ __device__ __forceinline__ void list_scatter_unit(
     }
     acc = wave_sum(acc);
     if (lane == 0) red[wid] = acc;
-    {
-        uint64_t lo[kRowsPerWave], hi[kRowsPerWave];
-        row_ballots<kRowsPerWave>(H, W, c0, y_rows, va, vb, lo, hi);
-        if (lane < kRowsPerWave) {
-            uint64_t ma = 0, mb = 0;
-#pragma unroll
-            for (int k = 0; k < kRowsPerWave; ++k) {
-                ma = lane == k ? lo[k] : ma;
-                mb = lane == k ? hi[k] : mb;
-            }
-            mlo[wid * kRowsPerWave + lane] = ma;
-            mhi[wid * kRowsPerWave + lane] = mb;
-        }
+    for (int e = t; e < kGroupStrips * kBandRows; e += 256) {
+        const int q = e / kBandRows, row = e % kBandRows;
+        start[row][q] = popc128(mlo[row], mhi[row], 8 * q, 8 * q + 8 + 2 * r);
     }
     __syncthreads();
     if (t == 0) {
@@ -354,85 +444,30 @@ __device__ __forceinline__ void list_scatter_unit(
             run += stot[q];
         }
     }
-    // (4) per-row counts of each strip of the group
-    for (int e = t; e < kGroupStrips * kBandRows; e += 256) {
-        const int q = e / kBandRows, row = e % kBandRows;
-        start[row][q] = popc128(mlo[row], mhi[row], 8 * q, 8 * q + 8 + 2 * r);
-    }
     __syncthreads();
     // (5) exclusive scan over the band's rows (lane = row): wave w scans
-    // strips w, w + 4
-    for (int q = wid; q < kGroupStrips; q += 4) {
+    // strips w, w + 4; the row offsets are stored after the records
+    int ro_val[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = wid + 4 * h;
         const bool rl = lane < kBandRows;
         const int v = rl ? start[rl ? lane : 0][q] : 0;
         const int incl = wave_inclusive_scan(v);
         const int st = sbase[q] + incl - v;
-        // kept for step (7) less the row's samples left of the strip's first
-        // halo column, so that a sample's index there is this plus its own
-        // rank in the row
+        ro_val[h] = st;
+        // kept for the records less the row's samples left of the strip's
+        // first halo column, so that a sample's index there is this plus
+        // its own rank in the row
         if (rl) start[lane][q] = st - popc128(mlo[lane], mhi[lane], 0, 8 * q);
-        const int s = s_first + q;
-        const int y = y_band + lane;
-        if (s < n_strips) {
-            int *ro = rowoff + (int64_t)s * (H + 1);
-            if (rl && y < H) ro[y] = st;
-            if (band == n_bands - 1 && lane == 0)
-                ro[H] = sbase[q] - spre[q] + stot[q];   // end of strip s
-        }
     }
     __syncthreads();
-    // (6) compact the band's valid pixels into plist (row << 8 | column),
-    // row by row: rowpos is the exclusive prefix of the rows' counts
-    if (wid == 0) {
-        const bool rl = lane < kBandRows;
-        const int row = rl ? lane : 0;
-        const int cnt = rl ? __builtin_popcountll(mlo[row]) + __builtin_popcountll(mhi[row])
-                           : 0;
-        const int incl = wave_inclusive_scan(cnt);
-        if (rl) rowpos[lane] = incl - cnt;
-        if (lane == 63) rowpos[kBandRows] = incl;
-    }
-    __syncthreads();
-    for (int row = wid; row < kBandRows; row += 4) {
-        const uint64_t ml = mlo[row], mh = mhi[row];
-        const int base = rowpos[row];
-        const uint32_t below =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(ml >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ml, 0u));
-        if ((ml >> lane) & 1ull) plist[base + below] = (uint16_t)((row << 8) | lane);
-        const uint32_t below_h =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(mh >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mh, 0u));
-        if ((mh >> lane) & 1ull)
-            plist[base + __builtin_popcountll(ml) + below_h] =
-                (uint16_t)((row << 8) | (64 + lane));
-    }
-    __syncthreads();
-    // (7) one thread per valid pixel (two per pass): load its colour and
-    // depth, then write its record into each strip of the group whose halo
+    // (6) records: each valid pixel into each strip of the group whose halo
     // holds it
     const int ts = table_stride(r);
-    const int total = rowpos[kBandRows];
     const int n_here = min(kGroupStrips, n_strips - s_first);
     for (int e0 = 0; e0 < total; e0 += 512) {
-        int ent[2];
-        bool ok[2];
-        uint32_t c01[2], c2[2], dd[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = e0 + 256 * u + t;
-            ok[u] = e < total;
-            ent[u] = plist[ok[u] ? e : 0];     // entry 0 exists: total > 0
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int row = ent[u] >> 8, lc = ent[u] & 255;
-            const int64_t p = (int64_t)(y_band + row) * W + (c0 + lc);
-            const uint8_t *c = rgb + 3 * p;
-            c01[u] = (uint32_t)c[0] | ((uint32_t)c[1] << 8);
-            c2[u] = c[2];
-            dd[u] = __float_as_uint(D[p]);
-        }
+        if (e0 > 0) load_pass(e0);
         // wait for these loads once, here: the store counter is the same
         // in-order counter as the load counter, so a load still pending at a
         // store (the depth word is stored as loaded) would make every record
@@ -440,9 +475,11 @@ __device__ __forceinline__ void list_scatter_unit(
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt/lgkmcnt any
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            if (!ok[u]) continue;
+            if (e0 + 256 * u + t >= total) continue;
             const int row = ent[u] >> 8, lc = ent[u] & 255;
             const int y = y_band + row;
+            if (reset_keys && lc >= r && lc < r + 64)   // one of the unit's own columns
+                reset_keys[(int64_t)y * W + (c0 + lc)] = kEmptyKey;
             uint32_t rg, b0;
             float nq2h;
             colour_fields(c01[u], c2[u], rg, b0, nq2h);
@@ -469,29 +506,35 @@ __device__ __forceinline__ void list_scatter_unit(
             }
         }
     }
+    // row offsets of strips w and w + 4 (lane = row), and each strip's end
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = wid + 4 * h;
+        const int s = s_first + q;
+        const int y = y_band + lane;
+        if (s < n_strips) {
+            int *ro = rowoff + (int64_t)s * (H + 1);
+            if (lane < kBandRows && y < H) ro[y] = ro_val[h];
+            if (band == n_bands - 1 && lane == 0)
+                ro[H] = sbase[q] - spre[q] + stot[q];   // end of strip s
+        }
+    }
 }
 
+// reset_keys (or null): the key image the decode read. A pixel is valid
+// exactly when its key is not the empty key, so writing the empty key back
+// at the valid pixels of each unit's own columns leaves the whole image
+// empty for the next projection.
 __global__ __launch_bounds__(256) void k_list_scatter(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
     int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
     int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs,
     uint64_t *__restrict__ reset_keys) {
+    int g, band;
+    list_unit((n_strips + kGroupStrips - 1) / kGroupStrips, n_bands, g, band);
     list_scatter_unit(D, B, rgb, H, W, r, n_strips, n_bands, bandcnt, grpcnt, rowoff,
-                      capacity, recs, blockIdx.x, blockIdx.y);
-    if (reset_keys) {
-        // the unit's own columns [64g, 64g + 64) of its band: no other unit
-        // reads them once the decode that precedes this kernel has finished
-        const int x = 64 * (int)blockIdx.x + (int)(threadIdx.x & 63);
-        const int y0 = (int)blockIdx.y * kBandRows;
-        if (x < W) {
-#pragma unroll
-            for (int k = (int)(threadIdx.x >> 6); k < kBandRows; k += 4) {
-                const int y = y0 + k;
-                if (y < H) reset_keys[(int64_t)y * W + x] = kEmptyKey;
-            }
-        }
-    }
+                      capacity, recs, g, band, reset_keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -931,7 +974,7 @@ hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
     ListViews v;
     if (!lists_possible(H, W, radius) || !list_views(ws, ws_bytes, L, v))
         return hipSuccess;  // nothing to build
-    const dim3 grid(L.n_groups, L.n_bands);
+    const int grid = L.n_groups * L.n_bands;   // units, see list_unit
     k_list_count<<<grid, 256, 0, s>>>(B, H, W, radius, L.n_strips, L.n_bands,
                                       v.bandcnt, v.grpcnt);
     k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, radius, L.n_strips,
@@ -1013,7 +1056,7 @@ hipError_t launch_project_densify(const float *pts, int64_t n, const Pose &pose,
     }
     hipError_t e = launch_project_keys(pts, n, pose, K, zbuf, s);
     if (e != hipSuccess) return e;
-    const dim3 grid(L.n_groups, L.n_bands);
+    const int grid = L.n_groups * L.n_bands;   // units, see list_unit
     k_decode_count<<<grid, 256, 0, s>>>(zbuf, H, W, fp.radius, L.n_strips, L.n_bands,
                                         D, B, v.bandcnt, v.grpcnt);
     k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, fp.radius, L.n_strips,
