@@ -183,8 +183,9 @@ jbfd_status jbfd_project(const float *pts_xyz, int64_t n,
  * jbfd_zbuf_clear and every call of this function leave it in (a buffer
  * fresh from jbfd_project holds the winning keys instead). The clearing
  * pass is skipped, and the decode writes the empty key back over each key
- * it reads, so the buffer is touched once less per frame and the winning
- * keys are not returned. sparse_depth and sparse_valid are required (NULL
+ * it reads that is not empty (the others are empty already), so the
+ * buffer is touched once less per frame and the winning keys are not
+ * returned. sparse_depth and sparse_valid are required (NULL
  * is JBFD_EINVAL); the other arguments are those of jbfd_project. Calls
  * that share a zbuf must be ordered (one stream, or synchronised).
  */
@@ -370,8 +371,8 @@ size_t jbfd_densify_backward_ws_bytes(int32_t H, int32_t W);
  * fixed-grid launches (project, decode, with JBFD_BATCH_LISTS list count and
  * list scatter, filter), each covering every view. Either form needs each
  * view's key buffer to hold only empty keys (UINT64_MAX) on entry, and
- * leaves it so (the decode writes the empty key back over each key it
- * reads): clear a new buffer once with jbfd_zbuf_clear. Either way every
+ * leaves it so (the decode writes the empty key back over each key that is
+ * not empty): clear a new buffer once with jbfd_zbuf_clear. Either way every
  * size is read from the table on the device,
  * so the launch(es) can be captured once into a HIP graph and replayed for
  * any batch written into the same device table, as long as every radius

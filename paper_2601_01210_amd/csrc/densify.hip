@@ -1199,7 +1199,8 @@ hipError_t launch_batch_filter(BatchHeader *hdr, const BatchView *views,
 // ---------------------------------------------------------------------------
 //
 // The key buffers hold only empty keys on entry (every batch run leaves
-// them so: its decode writes the empty key back over each key it reads), so
+// them so: its decode writes the empty key back over each key that is not
+// empty), so
 // the run has no clearing pass. Work items, numbered in this order (each
 // part view by view):
 //   [0, P)          projection chunks (kFusedPtChunk points),
@@ -1326,7 +1327,8 @@ __device__ inline void project_chunk(const BatchView &v, int c) {
 
 // keys of the chunk's pixels -> sparse depth (0 where empty) and 0/1 mask,
 // four consecutive pixels per thread and pass; the empty key is written
-// back over each key read (ordinary stores: only the next launch reads them)
+// back over each key that is not empty (ordinary stores: only the next
+// launch reads them)
 __device__ inline void decode_chunk(const BatchView &v, int c) {
     const int64_t npix = (int64_t)v.W * v.H;
     const bool vec = ((reinterpret_cast<uintptr_t>(v.sd) & 15) == 0) &&
@@ -1343,6 +1345,9 @@ __device__ inline void decode_chunk(const BatchView &v, int c) {
                 d[k] = hit ? (uint32_t)(key >> 32) : 0u;   // the bits of float Z, or +0
                 m |= (uint32_t)hit << (8 * k);
             }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((m >> (8 * k)) & 1u) v.zbuf[p0 + k] = kEmptyKey;
             // (two 8-byte stores: a 16-byte store with this cache policy
             // exists only as inline assembly, whose data registers the
             // compiler would not protect until the store has read them)
@@ -1351,16 +1356,13 @@ __device__ inline void decode_chunk(const BatchView &v, int c) {
             store_coherent(reinterpret_cast<uint64_t *>(v.sd + p0 + 2),
                            (uint64_t)d[2] | ((uint64_t)d[3] << 32));
             store_coherent(reinterpret_cast<uint32_t *>(v.sv + p0), m);
-            const ulonglong2 e = make_ulonglong2(kEmptyKey, kEmptyKey);
-            *reinterpret_cast<ulonglong2 *>(v.zbuf + p0) = e;
-            *reinterpret_cast<ulonglong2 *>(v.zbuf + p0 + 2) = e;
         } else {
             for (int64_t p = p0; p < npix && p < p0 + 4; ++p) {
                 const uint64_t key = load_coherent(v.zbuf + p);
                 const bool hit = key != kEmptyKey;
                 store_coherent(v.sd + p, hit ? __uint_as_float((uint32_t)(key >> 32)) : 0.0f);
                 store_coherent(v.sv + p, (uint8_t)hit);
-                v.zbuf[p] = kEmptyKey;
+                if (hit) v.zbuf[p] = kEmptyKey;
             }
         }
     }

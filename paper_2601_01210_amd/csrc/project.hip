@@ -85,8 +85,10 @@ __global__ __launch_bounds__(256) void k_project_motion(
 
 // Decode pixels [p0, min(p0+4, npix)): two 16-byte key loads, one 16-byte
 // depth store and one 4-byte mask store when aligned, else per pixel. With
-// RESET the empty key is written back over each key read, so the buffer
-// needs no clearing before the next projection into it.
+// RESET the empty key is written back over each key that is not empty, so
+// the buffer needs no clearing before the next projection into it (the
+// other keys are empty already; on a sparse image most lines of the key
+// buffer are then not written at all).
 template <bool RESET>
 __device__ inline void decode4(KeyPtr<RESET> keys, int64_t npix, int64_t p0, bool vec,
                                float *__restrict__ depth, uint8_t *__restrict__ valid) {
@@ -105,9 +107,8 @@ __device__ inline void decode4(KeyPtr<RESET> keys, int64_t npix, int64_t p0, boo
             *reinterpret_cast<float4 *>(depth + p0) = make_float4(d[0], d[1], d[2], d[3]);
         if (valid) *reinterpret_cast<uint32_t *>(valid + p0) = m;
         if constexpr (RESET) {
-            const ulonglong2 e = make_ulonglong2(kEmptyKey, kEmptyKey);
-            *reinterpret_cast<ulonglong2 *>(keys + p0) = e;
-            *reinterpret_cast<ulonglong2 *>(keys + p0 + 2) = e;
+            for (int t = 0; t < 4; ++t)
+                if (k[t] != kEmptyKey) keys[p0 + t] = kEmptyKey;
         }
     } else {
         for (int64_t p = p0; p < npix && p < p0 + 4; ++p) {
@@ -115,7 +116,8 @@ __device__ inline void decode4(KeyPtr<RESET> keys, int64_t npix, int64_t p0, boo
             const bool hit = k != kEmptyKey;
             if (depth) depth[p] = hit ? __uint_as_float((uint32_t)(k >> 32)) : 0.0f;
             if (valid) valid[p] = (uint8_t)hit;
-            if constexpr (RESET) keys[p] = kEmptyKey;
+            if constexpr (RESET)
+                if (hit) keys[p] = kEmptyKey;
         }
     }
 }
