@@ -549,6 +549,10 @@ __global__ __launch_bounds__(256) void k_list_scatter(
 // list. Capacities: samples of the tile's halo, samples of one block's.
 constexpr int kTileCap = 256;
 constexpr int kSubCap = 128;
+// Rounds of 256 halo pixels whose loads the staging issues together: three
+// covers the halo of a tile at r = 5 (676 pixels) and r = 15 (2116 pixels,
+// nine rounds) without an idle round.
+constexpr int kStageGroup = 3;
 
 // rounds of 256 pixels that cover a tile's halo at radius r <= RMAX
 template <int RMAX>
@@ -588,7 +592,7 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
                           const uint8_t *__restrict__ rgb, int H, int W, int r,
                           int tx, int ty, int bx, int by, FilterShared<RMAX, true> &sh) {
     constexpr int kMaxRounds = stage_rounds<RMAX>();
-    static_assert(kMaxRounds * kWaves <= 128 && kMaxRounds + 3 <= 32,
+    static_assert(kMaxRounds * kWaves <= 128 && kMaxRounds + kStageGroup - 1 <= 32,
                   "each wave scans the round counts, two per lane");
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -613,11 +617,11 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
     const uint32_t dxy_wrap = (1u << 16) - (uint32_t)rw;   // x - rw, y + 1
     __syncthreads();   // the previous tile's waves have read trec and tcnt
 
-    // (A) validity of each round's pixel, counted per (round, wave); four
-    // rounds' mask bytes are loaded together. (Loading the first rounds'
-    // sample data here already, to land under the count exchange, measured
-    // 7% slower on the eight-view batch: the registers it holds cost the
-    // kernel occupancy.)
+    // (A) validity of each round's pixel, counted per (round, wave); the
+    // mask bytes of kStageGroup rounds are loaded together. (Loading the
+    // first rounds' sample data here already, to land under the count
+    // exchange, measured 7% slower on the eight-view batch: the registers
+    // it holds cost the kernel occupancy.)
     uint32_t vbits = 0;
     auto load_sample = [&](uint32_t q, uint32_t &ac, float &ad) {
         const uint32_t o3 = q * 3u;
@@ -629,11 +633,11 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
     {
         int cx = cx0;
         uint32_t p = p0;
-        for (int j0 = 0; j0 < rounds; j0 += 4) {
-            uint32_t q[4];
-            bool in[4];
+        for (int j0 = 0; j0 < rounds; j0 += kStageGroup) {
+            uint32_t q[kStageGroup];
+            bool in[kStageGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kStageGroup; ++u) {
                 in[u] = (j0 + u) * 256 + tid < n;
                 q[u] = in[u] ? p : first;
                 cx += sx;
@@ -643,11 +647,11 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
                     p += dp_wrap;
                 }
             }
-            uint32_t m[4];
+            uint32_t m[kStageGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) m[u] = B[q[u]];
+            for (int u = 0; u < kStageGroup; ++u) m[u] = B[q[u]];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kStageGroup; ++u) {
                 const bool v = in[u] && m[u] != 0u;
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(v);
                 if (lane == 0 && j0 + u < rounds)
@@ -674,15 +678,15 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
     };
 
     // (B) records of the valid pixels at their ranks, the sample data of
-    // four rounds loaded together
+    // kStageGroup rounds loaded together
     {
         int cx = cx0;
         uint32_t p = p0, xy = xy0;
-        for (int j0 = 0; j0 < rounds; j0 += 4) {
-            uint32_t q[4], qxy[4];
-            bool v[4];
+        for (int j0 = 0; j0 < rounds; j0 += kStageGroup) {
+            uint32_t q[kStageGroup], qxy[kStageGroup];
+            bool v[kStageGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kStageGroup; ++u) {
                 v[u] = (vbits >> (j0 + u)) & 1u;
                 q[u] = p;
                 qxy[u] = xy;
@@ -695,16 +699,16 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
                     xy += dxy_wrap;
                 }
             }
-            uint32_t cc[4];   // colour bytes r | g << 8 | b << 16
-            float dd[4];
+            uint32_t cc[kStageGroup];   // colour bytes r | g << 8 | b << 16
+            float dd[kStageGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kStageGroup; ++u) {
                 cc[u] = 0u;
                 dd[u] = 0.0f;
                 if (v[u]) load_sample(q[u], cc[u], dd[u]);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kStageGroup; ++u) {
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(v[u]);
                 if (j0 + u < rounds && bal != 0u) {   // uniform
                     const int b0 = base_of(j0 + u);
