@@ -575,8 +575,8 @@ struct FilterShared<RMAX, true> {
     float G[(2 * RMAX + 15) * table_stride(RMAX)];
     Rec recs[kWaves][kSubCap];    // each wave's list (or its stream chunks)
     float nq2h[kWaves][kSubCap];
-    Rec trec[kTileCap];           // the tile halo's samples, xy = x | y << 16
-    float tq[kTileCap];
+    Rec trec[kTileCap];           // the tile halo's samples, xy = x | y << 16,
+                                  // rg = the colour bytes (unpacked per wave)
     int tcnt[stage_rounds<RMAX>() * kWaves];   // samples per (round, wave)
 };
 
@@ -717,12 +717,11 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
                                                  (uint32_t)(bal >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                         Rec rec;
-                        float q2h;
-                        colour_fields(cc[u] & 0xffffu, cc[u] >> 16, rec.rg, rec.b0, q2h);
                         rec.xy = qxy[u];
+                        rec.rg = cc[u];
+                        rec.b0 = 0u;
                         rec.d = dd[u];
                         sh.trec[pos] = rec;
-                        sh.tq[pos] = q2h;
                     }
                 }
             }
@@ -743,7 +742,6 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
         const int k = k0 + lane;
         const int kk = k < total ? k : 0;
         Rec rec = sh.trec[kk];
-        const float q2h = sh.tq[kk];
         const int x = (int)(rec.xy & 0xffffu), y = (int)(rec.xy >> 16);
         const bool mine = k < total && x >= hx0 && x < hx1 && y >= hy0 && y < hy1;
         const uint64_t bal = __builtin_amdgcn_ballot_w64(mine);
@@ -751,6 +749,11 @@ __device__ int tile_stage(const float *__restrict__ D, const uint8_t *__restrict
                                   (uint32_t)(bal >> 32),
                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
         if (mine && pos < kSubCap) {
+            // the colour fields are formed here, once per wave and sample,
+            // rather than for every lane of every staging round
+            const uint32_t c = rec.rg;
+            float q2h;
+            colour_fields(c & 0xffffu, c >> 16, rec.rg, rec.b0, q2h);
             rec.xy -= xoff;
             my[pos] = rec;
             myq[pos] = q2h;
