@@ -524,13 +524,19 @@ __device__ __forceinline__ void list_scatter_unit(
 // reset_keys (or null): the key image the decode read. A pixel is valid
 // exactly when its key is not the empty key, so writing the empty key back
 // at the valid pixels of each unit's own columns leaves the whole image
-// empty for the next projection.
+// empty for the next projection. table (or null): where to build the
+// filter's spatial table for sigma_s (ks in log2 units; weights: the FP16
+// range form's table of weights).
 __global__ __launch_bounds__(256) void k_list_scatter(
     const float *__restrict__ D, const uint8_t *__restrict__ B,
     const uint8_t *__restrict__ rgb, int H, int W, int r, int n_strips,
     int n_bands, const int *__restrict__ bandcnt, const int *__restrict__ grpcnt,
     int *__restrict__ rowoff, int64_t capacity, uint32_t *__restrict__ recs,
-    uint64_t *__restrict__ reset_keys) {
+    uint64_t *__restrict__ reset_keys, float *__restrict__ table, float ks,
+    bool weights) {
+    // the filter's spatial table for this call, built once by workgroup 0
+    // (the filter's workgroups copy it instead of building it each)
+    if (table && blockIdx.x == 0) build_table(table, r, table_stride(r), ks, weights);
     int g, band;
     list_unit((n_strips + kGroupStrips - 1) / kGroupStrips, n_bands, g, band);
     list_scatter_unit(D, B, rgb, H, W, r, n_strips, n_bands, bandcnt, grpcnt, rowoff,
@@ -792,7 +798,10 @@ __device__ __forceinline__ void filter_tile(const float *__restrict__ D,
     // spatial table: clamped exponents (FP32) or weights (FP16 range); a
     // caller whose previous tile had the same radius and sigma_s keeps it
     if (build) {
-        build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
+        if (la.table)   // uniform: built once for the call (list scatter)
+            copy_table(sh.G, la.table, r, ts);
+        else
+            build_table(sh.G, r, ts, fp.ks, PREC != JBFD_FP32);
         __syncthreads();
     }
     // without sample lists the workgroup stages the tile's halo once
@@ -986,7 +995,8 @@ hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
                                       v.bandcnt, v.grpcnt);
     k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, radius, L.n_strips,
                                         L.n_bands, v.bandcnt, v.grpcnt, v.rowoff,
-                                        v.capacity, v.recs, nullptr);
+                                        v.capacity, v.recs, nullptr, nullptr, 0.0f,
+                                        false);
     return hipGetLastError();
 }
 
@@ -994,7 +1004,7 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                           int32_t H, int32_t W, const FilterParams &fp,
                           jbfd_precision prec, float *out, uint8_t *mask,
                           float *aux, void *ws, size_t ws_bytes, bool lists_ready,
-                          hipStream_t s) {
+                          hipStream_t s, bool table_ready) {
     const int tiles_x = (W + kTile - 1) / kTile;
     const int tiles_y = (H + kTile - 1) / kTile;
     const int n_wg = column_grid(tiles_x, tiles_y);
@@ -1007,7 +1017,7 @@ hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                 launch_densify_prepare(D, B, rgb, H, W, fp.radius, ws, ws_bytes, s);
             if (e != hipSuccess) return e;
         }
-        la = ListArgs{v.recs, v.rowoff, v.capacity};
+        la = ListArgs{v.recs, v.rowoff, v.capacity, table_ready ? v.table : nullptr};
     }
     float2 *a2 = reinterpret_cast<float2 *>(aux);
     // with sample lists no staging (its LDS would cost the list walk
@@ -1068,11 +1078,12 @@ hipError_t launch_project_densify(const float *pts, int64_t n, const Pose &pose,
                                         D, B, v.bandcnt, v.grpcnt);
     k_list_scatter<<<grid, 256, 0, s>>>(D, B, rgb, H, W, fp.radius, L.n_strips,
                                         L.n_bands, v.bandcnt, v.grpcnt, v.rowoff,
-                                        v.capacity, v.recs, zbuf);
+                                        v.capacity, v.recs, zbuf, v.table, fp.ks,
+                                        prec != JBFD_FP32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_densify(D, B, rgb, H, W, fp, prec, out, mask, nullptr, ws, ws_bytes,
-                          true, s);
+                          true, s, true);
 }
 
 }  // namespace jbfd

@@ -140,10 +140,16 @@ struct ListLayout {
                      //   record of row y in strip s; [s][H] = end of strip s
     size_t bandcnt;  // int32 [n_strips][n_bands]: records per strip and band
     size_t grpcnt;   // int32 [n_groups][n_bands]: records per group and band
+    size_t table;    // float [kTableFloats]: the spatial table of the
+                     //   filter (build_table's layout), written by the list
+                     //   scatter of a call that knows sigma_s
     size_t recs;     // uint32 [capacity][kRecWords]
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// floats of the largest spatial table (radius JBFD_MAX_RADIUS)
+constexpr int kTableFloats = (2 * JBFD_MAX_RADIUS + 15) * table_stride(JBFD_MAX_RADIUS);
 
 inline ListLayout list_layout(int H, int W) {
     ListLayout L;
@@ -157,6 +163,8 @@ inline ListLayout list_layout(int H, int W) {
     off = align256(off + (size_t)L.n_strips * L.n_bands * 4);
     L.grpcnt = off;
     off = align256(off + (size_t)L.n_groups * L.n_bands * 4);
+    L.table = off;
+    off = align256(off + (size_t)kTableFloats * 4);
     L.recs = off;
     return L;
 }
@@ -182,6 +190,8 @@ struct ListArgs {
     const uint32_t *recs;   // nullptr: stream the halo instead
     const int *rowoff;      // [n_strips][H + 1]
     int64_t capacity;       // records the workspace holds
+    const float *table = nullptr;   // the spatial table built for this call
+                                    // (nullptr: each workgroup builds it)
 };
 
 // Pass-1 exponent of one sample (FP32 forms; the forward and the backward
@@ -263,6 +273,7 @@ __device__ inline void consume1(float t, float g, float d, float kr2, float &M,
 // views of a caller workspace
 struct ListViews {
     int *rowoff, *bandcnt, *grpcnt;
+    float *table;
     uint32_t *recs;
     int64_t capacity;
 };
@@ -274,6 +285,7 @@ inline bool list_views(void *ws, size_t ws_bytes, const ListLayout &L,
     v.rowoff = reinterpret_cast<int *>(w + L.rowoff);
     v.bandcnt = reinterpret_cast<int *>(w + L.bandcnt);
     v.grpcnt = reinterpret_cast<int *>(w + L.grpcnt);
+    v.table = reinterpret_cast<float *>(w + L.table);
     v.recs = reinterpret_cast<uint32_t *>(w + L.recs);
     v.capacity = (int64_t)((ws_bytes - L.recs) / (kRecWords * 4));
     return true;
@@ -685,6 +697,16 @@ __device__ inline void build_table(float *G, int r, int ts, float ks, bool weigh
         row1[h - ax] = g;
         row1[h + ax] = g;
     }
+}
+
+// The workgroup's copy of a table that build_table wrote to global memory
+// for this call (rows of ts floats, ts a multiple of 8: 16-byte loads and
+// LDS stores; the columns past 2r + 14 are never read, built or not).
+__device__ inline void copy_table(float *G, const float *__restrict__ src, int r, int ts) {
+    const int n4 = (2 * r + 15) * ts / 4;
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+    float4 *g4 = reinterpret_cast<float4 *>(G);
+    for (int e = (int)threadIdx.x; e < n4; e += 256) g4[e] = s4[e];
 }
 
 }  // namespace jbfd

@@ -44,11 +44,14 @@ hipError_t launch_project_densify(const float *pts, int64_t n, const Pose &pose,
                                   uint8_t *mask, void *ws, size_t ws_bytes,
                                   hipStream_t s);
 
+// table_ready: the workspace holds this call's spatial table (built by the
+// list scatter of jbfd_project_densify with the same radius, sigma_s and
+// precision)
 hipError_t launch_densify(const float *D, const uint8_t *B, const uint8_t *rgb,
                           int32_t H, int32_t W, const FilterParams &fp,
                           jbfd_precision prec, float *out, uint8_t *mask,
                           float *aux, void *ws, size_t ws_bytes, bool lists_ready,
-                          hipStream_t s);
+                          hipStream_t s, bool table_ready = false);
 
 hipError_t launch_densify_prepare(const float *D, const uint8_t *B,
                                   const uint8_t *rgb, int32_t H, int32_t W,
