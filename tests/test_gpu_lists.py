@@ -8,7 +8,8 @@ row and then column, every valid sample in its halo columns
 index of the first record of row y in strip s (rowoff[s][H] ends the strip).
 Records are bit-exact data moves, so the comparison is exact. The workspace
 offsets below restate the library's layout (rowoff, bandcnt and grpcnt
-blocks, each 256-byte aligned, then the records).
+blocks and room for the largest spatial table, each 256-byte aligned, then
+the records).
 """
 import numpy as np
 import pytest
@@ -36,6 +37,7 @@ def _layout(h, w):
     off = _align(n_strips * (h + 1) * 4)          # after rowoff
     off = _align(off + n_strips * n_bands * 4)    # after bandcnt
     off = _align(off + n_groups * n_bands * 4)    # after grpcnt
+    off = _align(off + (2 * 32 + 15) * _table_stride(32) * 4)   # after the table
     return n_strips, off
 
 
