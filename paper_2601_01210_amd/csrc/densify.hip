@@ -12,7 +12,7 @@
 // strips; the list of strip s holds, sorted by row and then column, every
 // valid sample in the strip's halo columns [8s-r, 8s+8+r), as a 20-byte
 // record {(r,g) f16x2, (b,0) f16x2, depth, -|rgb|^2 / 2, table word}. Two
-// kernels build all lists, each over (group of 8 strips) x (band of 16
+// kernels build all lists, each over (group of 8 strips) x (band of 32
 // rows) units:
 //   k_list_count    validity masks of the band's rows over the group's
 //                   halo columns (wave ballots) -> records per strip and band;
@@ -280,13 +280,13 @@ __device__ __forceinline__ void list_scatter_unit(
     const int s_first = kGroupStrips * g;
 
     // The prologue's loads are all issued before the first wait: (a) the
-    // validity bytes of the band's rows (wave w: rows 4w .. 4w+3), (b) the
+    // validity bytes of the band's rows (wave w: the w-th quarter), (b) the
     // group-and-band totals of the groups before g, whose sum is the number
     // of records of all strips before the group, and (c) per strip of the
     // group (32 threads each), its band counts, for its total and the part
     // in bands before ours. One batch of (b) and (c) covers images of up to
     // 2048 group-band entries before the group and 128 bands (Full-HD:
-    // 1972 and 68); larger images loop over further batches afterwards.
+    // 986 and 34); larger images loop over further batches afterwards.
     constexpr int kRowsPerWave = kBandRows / 4;
     const int y_rows = y_band + wid * kRowsPerWave;
     uint8_t va[kRowsPerWave], vb[kRowsPerWave];

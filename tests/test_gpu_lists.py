@@ -33,7 +33,7 @@ def _align(x):
 def _layout(h, w):
     n_strips = (w + 7) // 8
     n_groups = (n_strips + 7) // 8
-    n_bands = (h + 15) // 16
+    n_bands = (h + 31) // 32
     off = _align(n_strips * (h + 1) * 4)          # after rowoff
     off = _align(off + n_strips * n_bands * 4)    # after bandcnt
     off = _align(off + n_groups * n_bands * 4)    # after grpcnt
@@ -110,7 +110,7 @@ def test_lists_match_layout(torch_dev, case):
 
 
 def test_lists_fullhd_frame(torch_dev):
-    """The Full-HD single-view workload at r = 15 (30 groups x 68 bands)."""
+    """The Full-HD single-view workload at r = 15 (30 groups x 34 bands)."""
     torch, dev = torch_dev
     import oracle
     from paper_2601_01210_amd import densify_prepare, densify_workspace
