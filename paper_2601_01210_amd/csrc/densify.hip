@@ -1223,7 +1223,7 @@ hipError_t launch_batch_filter(BatchHeader *hdr, const BatchView *views,
 // part view by view):
 //   [0, P)          projection chunks (kFusedPtChunk points),
 //   [P, P + C)      decode chunks (kFusedPxChunk pixels),
-//   [P + C, ...)    filter items (kFusedTiles tiles of one row run each).
+//   [P + C, ...)    filter items (kFusedTiles consecutive tiles each).
 // An item waits only for earlier items of its own view: a decode chunk for
 // the view's projection chunks, a filter item for its decode chunks. Every
 // decode comes before every filter item in every queue, so a filter item

@@ -118,11 +118,12 @@ constexpr int kBatchChunk = 1024;
 // eight-view batch: decode items of 1024, 2048 and 4096 pixels measured
 // 0.256, 0.235 and 0.268 ms; projection items of 256, 512 and 1024 points
 // 0.228, 0.235 and 0.244 ms; 2, 4 and 8 filter tiles 0.239, 0.235 and
-// 0.260 ms.)
+// 0.260 ms, and then, with 256 points, 3 and 4 tiles 0.224 and 0.228 ms.)
 constexpr int kFusedPxChunk = 2048;   // pixels per decode item
 constexpr int kFusedPtChunk = 256;    // points per projection item (a
                                       // multiple of 256: one per thread)
-constexpr int kFusedTiles = 4;        // filter tiles per item (one row run)
+constexpr int kFusedTiles = 3;        // filter tiles per item (consecutive in
+                                      // the view's row-major tile order)
 // work queues, workgroup w uses w % kQueues (16, 32, 64 and 128 queues
 // measured 0.256, 0.250-0.255, 0.251 and 0.259 ms on the eight-view batch)
 constexpr int kQueues = 64;
