@@ -668,16 +668,18 @@ struct BlockWalker {
     }
 };
 
-// Fill the spatial table G[uy*ts + ux] (dx = ux - r - 7, dy = uy - r - 7)
-// with the clamped exponent -ks (dx^2+dy^2) >= -60 inside the window and
-// -inf outside (weights = false), or with the weight exp2(-ks (dx^2+dy^2))
+// Fill the spatial table G[uy*ts + ux] (dx = ux - r - 7, dy = uy - r - 7;
+// in LDS, or in a workspace for the filter's workgroups to copy) with the
+// clamped exponent -ks (dx^2+dy^2) >= -60 inside the window and -inf
+// outside (weights = false), or with the weight exp2(-ks (dx^2+dy^2))
 // floored at 2^-100 inside and 0 outside (weights = true).
 // The entries depend on |dx| and |dy| only: the workgroup's threads share
 // the quarter 0 <= |dx|, |dy| <= r + 7 and each writes its entry at the
 // four mirrored positions (about half the work of one entry per table
-// cell; the table is built by every workgroup, 8,160 times per Full-HD
-// frame). (float)(dx^2 + dy^2) is exact (below 2^24), so the entries equal
-// -ks (float)(dx^2 + dy^2), the exact pass's spatial exponents.
+// cell; without a table built for the call, every workgroup of the filter
+// builds its own, 8,160 times per Full-HD frame). (float)(dx^2 + dy^2) is
+// exact (below 2^24), so the entries equal -ks (float)(dx^2 + dy^2), the
+// exact pass's spatial exponents.
 __device__ inline void build_table(float *G, int r, int ts, float ks, bool weights) {
     const int h = r + 7;       // the centre's index in both directions
     const int q = h + 1;       // quarter side
